@@ -1,0 +1,213 @@
+/*
+ * bssn.h -- C ABI of the MI355X BSSN right-hand-side / RK4 library.
+ *
+ * The library evaluates the vacuum BSSN right-hand side of the Einstein
+ * Toolkit paper (arXiv:1111.3344, section "Spacetime Curvature Evolution":
+ * the BSSN definitions, the evolution equations for alpha, K, beta^i, B^i,
+ * phi, gt_ij, At_ij, Gt^i with m = 1, the Ricci split R~_ij + R^phi_ij, 1+log
+ * slicing and the Gamma-driver shift with the attenuation q(r)), discretised
+ * with centred finite differences of 4th (or 8th) order, upwinded advection
+ * for the partial_0 = partial_t - beta^j partial_j terms and Kreiss-Oliger
+ * dissipation (same section, opening paragraph), and fuses it with the
+ * stage update of a classical fourth-order Runge-Kutta method of lines
+ * (the paper separates right-hand-side evaluation from time integration:
+ * HydroBase's "Calculating the RHS in MoL" schedule group).
+ *
+ * General rules for every entry point:
+ *  - Device pointers point to HBM allocated by the caller (e.g. PyTorch);
+ *    host pointers are marked "host".  The library never frees, keeps or
+ *    allocates caller memory in the RK4 path.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All GPU work is enqueued asynchronously on it; kernel faults surface at
+ *    the caller's next synchronisation.
+ *  - Every call returns BSSN_OK or a negative BSSN_E* code and never throws.
+ *    Arguments are validated before anything is enqueued; a call that fails
+ *    validation enqueues nothing and leaves every output untouched.
+ *    bssn_last_error() gives a message for the last failure of the calling
+ *    host thread.
+ *  - Not thread-safe per stream: calls on one stream from several host
+ *    threads must be serialised by the caller.
+ *
+ * State layout (one "state buffer"): 25 float64 grid functions ("slots") in
+ * structure-of-arrays order, element (slot, z, y, x) of the storage grid
+ * (interior plus `ghost` layers on every face) at
+ *      ptr[slot*sf + z*sz + y*sy + x],   0 <= x < n[0]+2*ghost, etc.
+ * so ptr points to the ghost corner of slot 0 and x is contiguous.  For best
+ * performance sy should be a multiple of 16 and ptr + ghost 128-byte aligned.
+ * Slot order (the paper's evolved variables, phi-variant):
+ *   0 phi | 1-6 gt_xx gt_xy gt_xz gt_yy gt_yz gt_zz | 7 K |
+ *   8-13 At_xx At_xy At_xz At_yy At_yz At_zz | 14-16 Gt^x Gt^y Gt^z |
+ *   17 alpha | 18-20 beta^x beta^y beta^z | 21-23 B^x B^y B^z |
+ *   24 A (time-derivative variable of the lapse: zero source, advected and
+ *        dissipated only).
+ * Boundary handling: BSSN_BC_PERIODIC wraps stencil indices modulo n (ghost
+ * memory is never read or written); BSSN_BC_STATIC reads the ghost layers as
+ * fixed boundary data and writes interior points only, so the caller fills
+ * the ghosts of every buffer that is read by a stencil (u_n and every stage
+ * state) once, before the first stage.
+ */
+#ifndef BSSN_H
+#define BSSN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BSSN_ABI_VERSION 1
+
+enum {
+  BSSN_OK = 0,
+  BSSN_EINVAL = -1,      /* invalid argument (message in bssn_last_error)   */
+  BSSN_ENOMEM = -2,      /* device or host allocation failed                */
+  BSSN_EHIP = -3,        /* a HIP runtime call or launch failed             */
+  BSSN_ESTALE = -4,      /* a batch plan no longer matches its buffers      */
+  BSSN_EUNSUPPORTED = -5 /* valid request the library does not implement    */
+};
+
+enum { BSSN_FP64 = 0, BSSN_MIXED = 1 };            /* bssn_params.precision */
+enum { BSSN_BC_STATIC = 0, BSSN_BC_PERIODIC = 1 }; /* bssn_grid.bc          */
+enum { BSSN_NSLOT = 25 };
+
+/* A uniform Cartesian patch (the paper's CoordBase description: which points
+ * are evolved and which are set by boundary or symmetry conditions). */
+typedef struct {
+  int32_t n[3];       /* interior points along x, y, z; each >= 1            */
+  int32_t ghost;      /* ghost layers per face: >= 3 (order 4), >= 5 (8)     */
+  int64_t sy, sz, sf; /* element strides of a y-row, a z-plane, a slot;
+                         sy >= n[0]+2g, sz >= sy*(n[1]+2g), sf >= sz*(n[2]+2g)
+                         and 25*sf < 2^31                                     */
+  double origin[3];   /* coordinate of interior point (0,0,0)                */
+  double h[3];        /* grid spacing, > 0                                    */
+  int32_t bc;         /* BSSN_BC_STATIC or BSSN_BC_PERIODIC                  */
+} bssn_grid;
+
+/* Discretisation, precision and gauge parameters (gauge: the paper's 1+log
+ * slicing f = lapse_f/alpha with K_0 = 0, Gamma-driver G = shift_G/alpha^2,
+ * H = exp(4 phi), eta^i = eta q(r) B^i). */
+typedef struct {
+  int32_t fd_order;    /* 4 or 8                                              */
+  int32_t precision;   /* BSSN_FP64, or BSSN_MIXED: stencils and algebra in
+                          FP32 on differences taken from the centre value in
+                          FP64, state and RK4 update in FP64, and tiles whose
+                          minimum lapse is below fp64_alpha_threshold (near a
+                          puncture) evaluated entirely in FP64               */
+  double ko_eps;       /* Kreiss-Oliger strength, >= 0 (0.1)                 */
+  double lapse_f;      /* 2.0                                                 */
+  double shift_G;      /* 0.75                                                */
+  double eta;          /* 0.5                                                 */
+  double eta_R;        /* transition radius R of q(r) = min(1, R/r), r the
+                          coordinate radius; <= 0 or infinite: q = 1          */
+  int32_t lapse_static;/* 1: right-hand side of alpha forced to 0           */
+  int32_t shift_static;/* 1: right-hand sides of beta and B forced to 0     */
+  double fp64_alpha_threshold; /* BSSN_MIXED only (0.3)                       */
+} bssn_params;
+
+/* Version of this header the library was built from (BSSN_ABI_VERSION). */
+int bssn_abi_version(void);
+
+/* Message of the last failed call on this host thread; host memory owned by
+ * the library, valid until the next call on this thread; never NULL. */
+const char* bssn_last_error(void);
+
+/* Right-hand side d_t u of every slot at every interior point.
+ *   u    device, state buffer (read; ghosts read when bc is static)
+ *   rhs  device, same layout as u; interior points written, ghosts untouched;
+ *        must not alias u.
+ * Errors: BSSN_EINVAL (bad grid/params/pointers, aliasing), BSSN_EHIP. */
+int bssn_rhs(const bssn_grid* grid, const bssn_params* params,
+             const double* u, double* rhs, void* stream);
+
+/* Stage s (0..3) of classical RK4 (c = 0, 1/2, 1/2, 1; b = 1/6, 1/3, 1/3,
+ * 1/6), with k = d_t u(u_s) evaluated in the same kernel:
+ *   s = 0:  acc  = u_n + dt/6 k     u_out = u_n + dt/2 k     (u_s = u_n)
+ *   s = 1:  acc += dt/3 k           u_out = u_n + dt/2 k
+ *   s = 2:  acc += dt/3 k           u_out = u_n + dt   k
+ *   s = 3:                          u_out = acc + dt/6 k     (= u_{n+1})
+ * All buffers are device state buffers of the same layout; only interior
+ * points are written.  u_s may alias u_n (stage 0); u_out must not alias
+ * u_s or acc; acc must alias nothing; u_out may alias u_n only at stage 3.
+ * One step is stages 0..3 with (u_s, u_out) = (u_n, a), (a, b), (b, a),
+ * (a, u_n) for two scratch buffers a, b.
+ * Errors: BSSN_EINVAL (incl. stage outside 0..3, non-finite dt), BSSN_EHIP. */
+int rk4_stage(const bssn_grid* grid, const bssn_params* params, int stage,
+              double dt, const double* u_n, const double* u_s, double* acc,
+              double* u_out, void* stream);
+
+/* Hamiltonian and momentum constraints (section "Other analysis modules":
+ * H = R - K^i_j K^j_i + K^2, M_i = D_j K_i^j - D_i K, vacuum), evaluated in
+ * the BSSN variables in FP64 with the grid's finite-difference order, plus
+ * the conformal-connection constraint G^i = Gt^i - gt^jk Gt^i_jk.
+ *   u        device state buffer
+ *   H        device, 1 slot in the state layout (slot stride sf), or NULL
+ *   M        device, 3 slots in the state layout, or NULL
+ *   G        device, 3 slots in the state layout, or NULL
+ *   centres  host, 3*ncent coordinates (ncent 0..16); interior points closer
+ *            than r_exc to any centre are left out of the norms
+ *   norms    device, 8 doubles: H_rms, H_max, |M|_rms, |M|_max, |G|_rms,
+ *            |G|_max, N_used, N_nonfinite (rms = sqrt(sum/N_used) over used
+ *            points with finite values; |M| the flat Euclidean norm).
+ * The reduction order is fixed, so results are bitwise reproducible.  The
+ * first call on a device allocates a small partial-sum workspace that lives
+ * until the process ends.
+ * Errors: BSSN_EINVAL, BSSN_ENOMEM, BSSN_EHIP. */
+int bssn_constraints(const bssn_grid* grid, const bssn_params* params,
+                     const double* u, double* H, double* M, double* G,
+                     const double* centres, int ncent, double r_exc,
+                     double* norms, void* stream);
+
+/* Number of tiles a BSSN_MIXED evaluation of u runs in FP64 (tiles whose
+ * minimum lapse is below params->fp64_alpha_threshold) and the total number
+ * of tiles.  Synchronous; n_fp64 and n_tiles are host pointers. */
+int bssn_mixed_tile_count(const bssn_grid* grid, const bssn_params* params,
+                          const double* u, int64_t* n_fp64, int64_t* n_tiles,
+                          void* stream);
+
+/* ---- many uneven patches advanced together (the paper's mesh-refinement
+ * components: many independent grids per level) ------------------------ */
+typedef struct bssn_batch_plan bssn_batch_plan;
+
+/* Build a plan for npatch independent static-boundary patches sharing one
+ * bssn_params and one dt.  Per patch p (host arrays of device pointers):
+ *   grids[p]  host, the patch's grid (bc must be BSSN_BC_STATIC)
+ *   u[p]      device state buffer holding u_n; receives u_{n+1} after each
+ *             step
+ *   a[p], b[p]  device scratch state buffers with the same ghosts as u[p]
+ *   acc[p]    device scratch state buffer (ghosts unused)
+ * autotune = 1 times candidate tile shapes per patch size class on the
+ * given buffers (their contents are not modified in a way visible after the
+ * plan is built: tuning runs stage 0 only, which writes a and acc) and keeps
+ * the fastest; 0 uses the default shape.  The plan records all work as one
+ * persistent kernel per RK4 stage and captures the four stages of a step
+ * in a hipGraph.  It stores copies of the pointer arrays; the buffers must
+ * stay allocated while the plan lives.
+ * Errors: BSSN_EINVAL, BSSN_ENOMEM, BSSN_EHIP. */
+int batch_patches_plan(int npatch, const bssn_grid* grids,
+                       const bssn_params* params, double* const* u,
+                       double* const* a, double* const* b,
+                       double* const* acc, double dt, int autotune,
+                       bssn_batch_plan** plan, void* stream);
+
+/* Advance every patch of the plan by nsteps RK4 steps (one graph launch per
+ * step on `stream`).  Returns BSSN_ESTALE if the plan was invalidated. */
+int batch_patches(bssn_batch_plan* plan, int nsteps, void* stream);
+
+/* Same update without the persistent kernel or graph: one kernel launch per
+ * patch and stage (the baseline the batched path is measured against). */
+int batch_patches_unbatched(bssn_batch_plan* plan, int nsteps, void* stream);
+
+/* Tile shape chosen for each size class: writes up to max_classes entries of
+ * (class extent, tile_x, tile_y) triples into host array out; returns the
+ * number of classes (>= 0) or an error code. */
+int batch_patches_describe(const bssn_batch_plan* plan, int max_classes,
+                           int32_t* out);
+
+/* Release the plan (its graph, work list and device copies). */
+int batch_patches_destroy(bssn_batch_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSSN_H */

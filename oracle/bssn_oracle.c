@@ -47,6 +47,7 @@
  * Compiled with -O2 -fopenmp -ffp-contract=off -fno-fast-math.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -806,3 +807,6 @@ int oracle_point_ops(const oracle_grid* g, const oracle_params* P,
   for (int a = 0; a < 3; ++a) out[15 + a] = ko(g, u, f, p, a, P->ko_eps, ord);
   return 0;
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int oracle_num_threads(void) { return omp_get_max_threads(); }

@@ -46,6 +46,7 @@ def lib():
         _lib.oracle_rk4_step.argtypes = [g, p, ctypes.c_double, d, d]
         _lib.oracle_constraints.argtypes = [g, p, d, d, d, d, d, ctypes.c_int,
                                             ctypes.c_double, d]
+        _lib.oracle_num_threads.restype = ctypes.c_int
         _lib.oracle_point_ops.argtypes = [g, p, d, ctypes.c_int,
                                           P(ctypes.c_int32), d, d]
     return _lib
@@ -154,3 +155,7 @@ def point_ops(grid, prm, u, slot, p, beta=(1.0, 1.0, 1.0)):
         _ptr(out, 0)), "point_ops")
     return dict(d1=out[0:3], d2=out[3:12].reshape(3, 3), up=out[12:15],
                 ko=out[15:18])
+
+
+def num_threads():
+    return lib().oracle_num_threads()

@@ -1,0 +1,262 @@
+"""Python binding of the C ABI in include/bssn.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls; all GPU work
+runs in the HIP library (libbssn_hip.so, built in-tree by build.py).  There
+is no fallback: if the library is missing, loading raises.
+
+State buffers are flat torch float64 tensors on the GPU laid out as described
+in ``paper_1111_3344_amd.inputs`` (front pad ``grid.off0`` elements, then 25
+slots); the pointer handed to the library is the ghost corner of slot 0.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbssn_hip.so")
+
+BSSN_OK, BSSN_EINVAL, BSSN_ENOMEM, BSSN_EHIP, BSSN_ESTALE, \
+    BSSN_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+BSSN_FP64, BSSN_MIXED = 0, 1
+BSSN_BC_STATIC, BSSN_BC_PERIODIC = 0, 1
+
+
+class BssnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class bssn_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("ghost", ctypes.c_int32),
+                ("sy", ctypes.c_int64), ("sz", ctypes.c_int64),
+                ("sf", ctypes.c_int64), ("origin", ctypes.c_double * 3),
+                ("h", ctypes.c_double * 3), ("bc", ctypes.c_int32)]
+
+
+class bssn_params(ctypes.Structure):
+    _fields_ = [("fd_order", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("ko_eps", ctypes.c_double), ("lapse_f", ctypes.c_double),
+                ("shift_G", ctypes.c_double), ("eta", ctypes.c_double),
+                ("eta_R", ctypes.c_double), ("lapse_static", ctypes.c_int32),
+                ("shift_static", ctypes.c_int32),
+                ("fp64_alpha_threshold", ctypes.c_double)]
+
+
+@dataclasses.dataclass
+class Params:
+    """bssn_params with the paper's gauge defaults."""
+    fd_order: int = 4
+    precision: int = BSSN_FP64
+    ko_eps: float = 0.1
+    lapse_f: float = 2.0
+    shift_G: float = 0.75
+    eta: float = 0.5
+    eta_R: float = 0.0
+    lapse_static: int = 0
+    shift_static: int = 0
+    fp64_alpha_threshold: float = 0.3
+
+    def c(self):
+        p = bssn_params()
+        for f in dataclasses.fields(self):
+            setattr(p, f.name, getattr(self, f.name))
+        return p
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with "
+                "paper_1111_3344_amd.build.build() (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        g, p = P(bssn_grid), P(bssn_params)
+        L.bssn_abi_version.restype = ctypes.c_int
+        L.bssn_last_error.restype = ctypes.c_char_p
+        L.bssn_rhs.argtypes = [g, p, vp, vp, vp]
+        L.rk4_stage.argtypes = [g, p, ctypes.c_int, ctypes.c_double, vp, vp,
+                                vp, vp, vp]
+        L.bssn_constraints.argtypes = [g, p, vp, vp, vp, vp,
+                                       P(ctypes.c_double), ctypes.c_int,
+                                       ctypes.c_double, vp, vp]
+        L.bssn_mixed_tile_count.argtypes = [g, p, vp, P(ctypes.c_int64),
+                                            P(ctypes.c_int64), vp]
+        if hasattr(L, "batch_patches_plan"):
+            L.batch_patches_plan.argtypes = [
+                ctypes.c_int, P(bssn_grid), p, P(vp), P(vp), P(vp), P(vp),
+                ctypes.c_double, ctypes.c_int, P(vp), vp]
+            L.batch_patches.argtypes = [vp, ctypes.c_int, vp]
+            L.batch_patches_unbatched.argtypes = [vp, ctypes.c_int, vp]
+            L.batch_patches_describe.argtypes = [vp, ctypes.c_int,
+                                                 P(ctypes.c_int32)]
+            L.batch_patches_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def c_grid(grid):
+    """bssn_grid from a GridSpec-like object."""
+    s = bssn_grid()
+    s.n[:] = list(grid.n)
+    s.ghost = grid.ghost
+    s.sy, s.sz, s.sf = grid.sy, grid.sz, grid.sf
+    s.origin[:] = list(grid.origin)
+    s.h[:] = list(grid.h)
+    s.bc = grid.bc
+    return s
+
+
+def _params(prm):
+    if prm is None:
+        prm = Params()
+    if isinstance(prm, dict):
+        prm = Params(**prm)
+    return prm.c()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def ptr(grid, t):
+    """Device address of the ghost corner of slot 0 of flat tensor t."""
+    if t is None:
+        return None
+    if t.dtype.itemsize != 8:
+        raise TypeError("state buffers are float64")
+    return ctypes.c_void_p(t.data_ptr() + 8 * grid.off0)
+
+
+def _check(rc):
+    if rc != BSSN_OK:
+        raise BssnError(rc, bssn_last_error())
+
+
+def bssn_abi_version():
+    return lib().bssn_abi_version()
+
+
+def bssn_last_error():
+    return lib().bssn_last_error().decode()
+
+
+def bssn_rhs(grid, params, u, rhs, stream=None):
+    _check(lib().bssn_rhs(ctypes.byref(c_grid(grid)),
+                          ctypes.byref(_params(params)), ptr(grid, u),
+                          ptr(grid, rhs), _stream(stream)))
+
+
+def rk4_stage(grid, params, stage, dt, u_n, u_s, acc, u_out, stream=None):
+    _check(lib().rk4_stage(ctypes.byref(c_grid(grid)),
+                           ctypes.byref(_params(params)), int(stage),
+                           float(dt), ptr(grid, u_n), ptr(grid, u_s),
+                           ptr(grid, acc), ptr(grid, u_out), _stream(stream)))
+
+
+def rk4_step(grid, params, dt, u, a, b, acc, stream=None):
+    """One classical RK4 step in place on u (four rk4_stage calls)."""
+    rk4_stage(grid, params, 0, dt, u, u, acc, a, stream)
+    rk4_stage(grid, params, 1, dt, u, a, acc, b, stream)
+    rk4_stage(grid, params, 2, dt, u, b, acc, a, stream)
+    rk4_stage(grid, params, 3, dt, u, a, acc, u, stream)
+
+
+def bssn_constraints(grid, params, u, norms, H=None, M=None, G=None,
+                     centres=(), r_exc=0.0, stream=None):
+    """norms: device float64 tensor of >= 8 elements; H/M/G: flat state-shaped
+    tensors (their slots 0, 0..2, 0..2 receive the fields) or None."""
+    flat = [float(v) for c in centres for v in c]
+    arr = (ctypes.c_double * max(1, len(flat)))(*flat)
+    _check(lib().bssn_constraints(
+        ctypes.byref(c_grid(grid)), ctypes.byref(_params(params)),
+        ptr(grid, u), ptr(grid, H), ptr(grid, M), ptr(grid, G), arr,
+        len(flat) // 3, float(r_exc), ctypes.c_void_p(norms.data_ptr()),
+        _stream(stream)))
+
+
+def bssn_mixed_tile_count(grid, params, u, stream=None):
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().bssn_mixed_tile_count(
+        ctypes.byref(c_grid(grid)), ctypes.byref(_params(params)),
+        ptr(grid, u), ctypes.byref(a), ctypes.byref(b), _stream(stream)))
+    return a.value, b.value
+
+
+class BatchPlan:
+    """Owner of a bssn_batch_plan*; the buffers must outlive it."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def __del__(self):
+        self.destroy()
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib().batch_patches_destroy(self.handle)
+            self.handle = None
+
+
+def batch_patches_plan(grids, params, u, a, b, acc, dt, autotune=True,
+                       stream=None):
+    n = len(grids)
+    G = (bssn_grid * n)(*[c_grid(g) for g in grids])
+    arrs = []
+    for bufs in (u, a, b, acc):
+        arrs.append((ctypes.c_void_p * n)(*[ptr(g, t) for g, t in
+                                             zip(grids, bufs)]))
+    h = ctypes.c_void_p()
+    _check(lib().batch_patches_plan(n, G, ctypes.byref(_params(params)),
+                                    arrs[0], arrs[1], arrs[2], arrs[3],
+                                    float(dt), int(bool(autotune)),
+                                    ctypes.byref(h), _stream(stream)))
+    return BatchPlan(h, (u, a, b, acc))
+
+
+def batch_patches(plan, nsteps, stream=None):
+    _check(lib().batch_patches(plan.handle, int(nsteps), _stream(stream)))
+
+
+def batch_patches_unbatched(plan, nsteps, stream=None):
+    _check(lib().batch_patches_unbatched(plan.handle, int(nsteps),
+                                         _stream(stream)))
+
+
+def batch_patches_describe(plan, max_classes=64):
+    out = (ctypes.c_int32 * (3 * max_classes))()
+    n = lib().batch_patches_describe(plan.handle, max_classes, out)
+    if n < 0:
+        raise BssnError(n, bssn_last_error())
+    return [tuple(out[3 * i:3 * i + 3]) for i in range(n)]
+
+
+def batch_patches_destroy(plan):
+    plan.destroy()
+
+
+# ---- device buffers -------------------------------------------------------
+def to_device(flat, device="cuda"):
+    import torch
+    return torch.from_numpy(flat).to(device)
+
+
+def empty_state(grid, device="cuda"):
+    import torch
+    return torch.zeros(grid.total, dtype=torch.float64, device=device)

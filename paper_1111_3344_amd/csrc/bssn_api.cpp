@@ -1,0 +1,299 @@
+// bssn_api.cpp -- the extern "C" entry points of include/bssn.h: argument
+// validation (before anything is enqueued), error reporting and dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bssn.h"
+#include "bssn_api_internal.h"
+#include "bssn_internal.h"
+#include "bssn_kernels.h"
+
+namespace bssn {
+
+static thread_local std::string g_err = "no error";
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(BSSN_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_grid(const bssn_grid* g, int order) {
+  if (!g) return fail(BSSN_EINVAL, "grid is NULL");
+  const int need = order == 8 ? 5 : 3;
+  for (int a = 0; a < 3; ++a) {
+    if (g->n[a] < 1) return fail(BSSN_EINVAL, "grid.n[%d] = %d < 1", a, g->n[a]);
+    if (!(g->h[a] > 0.0) || !std::isfinite(g->h[a]))
+      return fail(BSSN_EINVAL, "grid.h[%d] must be finite and > 0", a);
+    if (!std::isfinite(g->origin[a]))
+      return fail(BSSN_EINVAL, "grid.origin[%d] is not finite", a);
+  }
+  if (g->ghost < need)
+    return fail(BSSN_EINVAL, "grid.ghost = %d < %d required by order %d",
+                g->ghost, need, order);
+  if (g->bc != BSSN_BC_STATIC && g->bc != BSSN_BC_PERIODIC)
+    return fail(BSSN_EINVAL, "grid.bc = %d is not a BSSN_BC_* value", g->bc);
+  if (g->bc == BSSN_BC_PERIODIC)
+    for (int a = 0; a < 3; ++a)
+      if (g->n[a] < need)
+        return fail(BSSN_EINVAL,
+                    "periodic grid.n[%d] = %d below the stencil reach %d", a,
+                    g->n[a], need);
+  const int64_t ex = g->n[0] + 2LL * g->ghost, ey = g->n[1] + 2LL * g->ghost,
+                ez = g->n[2] + 2LL * g->ghost;
+  if (g->sy < ex) return fail(BSSN_EINVAL, "grid.sy < n[0] + 2 ghost");
+  if (g->sz < g->sy * ey) return fail(BSSN_EINVAL, "grid.sz < sy (n[1] + 2 ghost)");
+  if (g->sf < g->sz * ez) return fail(BSSN_EINVAL, "grid.sf < sz (n[2] + 2 ghost)");
+  if (g->sf * 8 > 0x7fffffffLL)
+    return fail(BSSN_EUNSUPPORTED, "one slot exceeds 2 GiB (sf = %lld)",
+                (long long)g->sf);
+  return BSSN_OK;
+}
+
+int check_params(const bssn_params* p) {
+  if (!p) return fail(BSSN_EINVAL, "params is NULL");
+  if (p->fd_order != 4 && p->fd_order != 8)
+    return fail(BSSN_EINVAL, "params.fd_order = %d (4 or 8)", p->fd_order);
+  if (p->precision != BSSN_FP64 && p->precision != BSSN_MIXED)
+    return fail(BSSN_EINVAL, "params.precision = %d", p->precision);
+  const double v[] = {p->ko_eps, p->lapse_f, p->shift_G, p->eta};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(BSSN_EINVAL, "non-finite gauge parameter");
+  if (p->ko_eps < 0) return fail(BSSN_EINVAL, "params.ko_eps < 0");
+  if (std::isnan(p->eta_R)) return fail(BSSN_EINVAL, "params.eta_R is NaN");
+  if ((p->lapse_static != 0 && p->lapse_static != 1) ||
+      (p->shift_static != 0 && p->shift_static != 1))
+    return fail(BSSN_EINVAL, "lapse_static / shift_static must be 0 or 1");
+  if (p->precision == BSSN_MIXED && std::isnan(p->fp64_alpha_threshold))
+    return fail(BSSN_EINVAL, "fp64_alpha_threshold is NaN");
+  return BSSN_OK;
+}
+
+Patch make_patch(const bssn_grid* g) {
+  Patch P{};
+  for (int a = 0; a < 3; ++a) {
+    P.n[a] = g->n[a];
+    P.origin[a] = g->origin[a];
+    P.h[a] = g->h[a];
+  }
+  P.ghost = g->ghost;
+  P.sy = int32_t(g->sy);
+  P.sz = int32_t(g->sz);
+  P.sf = g->sf;
+  return P;
+}
+
+Gauge make_gauge(const bssn_params* p) {
+  Gauge G{};
+  G.ko_eps = p->ko_eps;
+  G.lapse_f = p->lapse_f;
+  G.shift_G = p->shift_G;
+  G.eta = p->eta;
+  G.eta_R = (p->eta_R > 0 && std::isfinite(p->eta_R)) ? p->eta_R : 0.0;
+  G.lapse_static = p->lapse_static;
+  G.shift_static = p->shift_static;
+  G.alpha_thr = p->fp64_alpha_threshold;
+  return G;
+}
+
+}  // namespace bssn
+
+using namespace bssn;
+
+extern "C" {
+
+int bssn_abi_version(void) { return BSSN_ABI_VERSION; }
+
+const char* bssn_last_error(void) { return g_err.c_str(); }
+
+int bssn_rhs(const bssn_grid* grid, const bssn_params* params, const double* u,
+             double* rhs, void* stream) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  if ((rc = check_grid(grid, params->fd_order))) return rc;
+  if (!u || !rhs) return fail(BSSN_EINVAL, "u and rhs must be non-NULL");
+  if (u == rhs) return fail(BSSN_EINVAL, "rhs must not alias u");
+  Patch P = make_patch(grid);
+  P.u_s = u;
+  P.u_n = u;
+  P.acc = nullptr;
+  P.out = rhs;
+  P.dt = 0.0;
+  hipError_t e = launch_stage(P, make_gauge(params), params->fd_order,
+                              grid->bc == BSSN_BC_PERIODIC, ST_RHS,
+                              params->precision, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "bssn_rhs launch");
+  g_err = "no error";
+  return BSSN_OK;
+}
+
+int rk4_stage(const bssn_grid* grid, const bssn_params* params, int stage,
+              double dt, const double* u_n, const double* u_s, double* acc,
+              double* u_out, void* stream) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  if ((rc = check_grid(grid, params->fd_order))) return rc;
+  if (stage < 0 || stage > 3)
+    return fail(BSSN_EINVAL, "stage = %d outside 0..3", stage);
+  if (!std::isfinite(dt)) return fail(BSSN_EINVAL, "dt is not finite");
+  if (!u_n || !u_s || !acc || !u_out)
+    return fail(BSSN_EINVAL, "u_n, u_s, acc and u_out must be non-NULL");
+  if (u_out == u_s) return fail(BSSN_EINVAL, "u_out must not alias u_s");
+  if (acc == u_n || acc == u_s || acc == u_out)
+    return fail(BSSN_EINVAL, "acc must not alias any other buffer");
+  if (u_out == u_n && stage != 3)
+    return fail(BSSN_EINVAL, "u_out may alias u_n only at stage 3");
+  Patch P = make_patch(grid);
+  P.u_s = u_s;
+  P.u_n = u_n;
+  P.acc = acc;
+  P.out = u_out;
+  P.dt = dt;
+  hipError_t e = launch_stage(P, make_gauge(params), params->fd_order,
+                              grid->bc == BSSN_BC_PERIODIC, stage,
+                              params->precision, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rk4_stage launch");
+  g_err = "no error";
+  return BSSN_OK;
+}
+
+}  // extern "C"
+
+// ---- workspaces that live until the process ends ---------------------------------
+namespace bssn {
+namespace {
+struct DeviceWs {
+  double* partials = nullptr;
+  size_t partials_n = 0;  // records of 8 doubles
+  unsigned long long* counter = nullptr;
+};
+std::mutex g_ws_mu;
+std::vector<DeviceWs> g_ws;
+
+int device_ws(DeviceWs** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+  *out = &g_ws[dev];
+  return BSSN_OK;
+}
+}  // namespace
+}  // namespace bssn
+
+extern "C" {
+
+int bssn_constraints(const bssn_grid* grid, const bssn_params* params,
+                     const double* u, double* H, double* M, double* G,
+                     const double* centres, int ncent, double r_exc,
+                     double* norms, void* stream) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  if ((rc = check_grid(grid, params->fd_order))) return rc;
+  if (!u || !norms) return fail(BSSN_EINVAL, "u and norms must be non-NULL");
+  if (ncent < 0 || ncent > 16)
+    return fail(BSSN_EINVAL, "ncent = %d outside 0..16", ncent);
+  if (ncent > 0 && !centres)
+    return fail(BSSN_EINVAL, "centres is NULL with ncent > 0");
+  if (std::isnan(r_exc)) return fail(BSSN_EINVAL, "r_exc is NaN");
+  const double* outs[3] = {H, M, G};
+  for (const double* o : outs)
+    if (o && o == u) return fail(BSSN_EINVAL, "outputs must not alias u");
+  ConstraintArgs A{};
+  A.u = u;
+  A.H = H;
+  A.M = M;
+  A.Gc = G;
+  for (int a = 0; a < 3; ++a) {
+    A.n[a] = grid->n[a];
+    A.origin[a] = grid->origin[a];
+    A.h[a] = grid->h[a];
+  }
+  A.ghost = grid->ghost;
+  A.sy = int32_t(grid->sy);
+  A.sz = int32_t(grid->sz);
+  A.sf = grid->sf;
+  A.periodic = grid->bc == BSSN_BC_PERIODIC;
+  A.ncent = ncent;
+  for (int c = 0; c < ncent; ++c)
+    for (int a = 0; a < 3; ++a) A.centres[c][a] = centres[3 * c + a];
+  A.r_exc = r_exc;
+  DeviceWs* ws = nullptr;
+  if ((rc = device_ws(&ws))) return rc;
+  const size_t nb = size_t(constraint_blocks(A));
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if (ws->partials_n < nb) {
+      // the old workspace may still be read by enqueued work
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+      if (ws->partials) (void)hipFree(ws->partials);
+      ws->partials = nullptr;
+      ws->partials_n = 0;
+      const size_t want = nb < 65536 ? 65536 : nb;
+      e = hipMalloc((void**)&ws->partials, want * 8 * sizeof(double));
+      if (e != hipSuccess) return fail(BSSN_ENOMEM, "workspace: %s", hipGetErrorString(e));
+      ws->partials_n = want;
+    }
+  }
+  hipError_t e = launch_constraints(A, params->fd_order, ws->partials,
+                                    int(ws->partials_n), norms,
+                                    (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "bssn_constraints launch");
+  g_err = "no error";
+  return BSSN_OK;
+}
+
+int bssn_mixed_tile_count(const bssn_grid* grid, const bssn_params* params,
+                          const double* u, int64_t* n_fp64, int64_t* n_tiles,
+                          void* stream) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  if ((rc = check_grid(grid, params->fd_order))) return rc;
+  if (!u || !n_fp64 || !n_tiles)
+    return fail(BSSN_EINVAL, "u, n_fp64 and n_tiles must be non-NULL");
+  DeviceWs* ws = nullptr;
+  if ((rc = device_ws(&ws))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if (!ws->counter) {
+      hipError_t e = hipMalloc((void**)&ws->counter, sizeof(unsigned long long));
+      if (e != hipSuccess) return fail(BSSN_ENOMEM, "counter: %s", hipGetErrorString(e));
+    }
+  }
+  Patch P = make_patch(grid);
+  P.u_s = u;
+  hipError_t e = hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), st);
+  if (e == hipSuccess)
+    e = launch_tile_count(P, params->fp64_alpha_threshold, ws->counter, st);
+  unsigned long long h = 0;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&h, ws->counter, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "bssn_mixed_tile_count");
+  dim3 grd, blk;
+  tile_grid(P, grd, blk);
+  *n_fp64 = (int64_t)h;
+  *n_tiles = (int64_t)grd.x * grd.y * grd.z;
+  g_err = "no error";
+  return BSSN_OK;
+}
+
+}  // extern "C"

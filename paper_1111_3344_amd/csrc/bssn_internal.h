@@ -1,0 +1,45 @@
+// bssn_internal.h -- structures shared by the HIP kernels and the C-ABI glue
+// (not part of the public ABI).
+#pragma once
+#include <stdint.h>
+
+namespace bssn {
+
+constexpr int NSLOT = 25;
+
+// slot numbers (see include/bssn.h)
+enum : int {
+  PHI = 0, GXX = 1, GXY, GXZ, GYY, GYZ, GZZ, TRK = 7, AXX = 8, AXY, AXZ,
+  AYY, AYZ, AZZ, GAMX = 14, GAMY, GAMZ, ALP = 17, BETX = 18, BETY, BETZ,
+  BX = 21, BY, BZ, ADOT = 24
+};
+
+// What a stage kernel writes.
+enum : int { ST_RHS = -1, ST_0 = 0, ST_1 = 1, ST_2 = 2, ST_3 = 3 };
+
+// Which points a mixed-precision kernel takes: all, only tiles whose minimum
+// lapse is >= the threshold (FP32 path), or only the others (FP64 path).
+enum : int { TILE_ALL = 0, TILE_FP32 = 1, TILE_FP64 = 2 };
+
+// One patch as the kernels see it.
+struct Patch {
+  const double* u_s;   // stage input (stencil reads)
+  const double* u_n;   // step start (stages 0..2)
+  double* acc;         // RK4 accumulator
+  double* out;         // stage output (or the RHS for ST_RHS)
+  int32_t n[3];
+  int32_t ghost;
+  int32_t sy, sz;      // element strides (fit 32 bits: a slot < 2 GB)
+  int64_t sf;
+  double origin[3];
+  double h[3];
+  double dt;
+};
+
+struct Gauge {
+  double ko_eps, lapse_f, shift_G, eta, eta_R;  // eta_R <= 0: q = 1
+  int32_t lapse_static, shift_static;
+  double alpha_thr;
+};
+
+}  // namespace bssn

@@ -1,0 +1,49 @@
+// bssn_kernels.h -- host-side launchers implemented in the .hip files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "bssn_internal.h"
+
+namespace bssn {
+
+// One RK4 stage (or the bare RHS for stage ST_RHS) on one patch.
+// precision 0: FP64; 1: FP32 tiles + FP64 tiles (two launches).
+hipError_t launch_stage_o4(const Patch& P, const Gauge& G, int periodic,
+                           int stage, int precision, hipStream_t st);
+hipError_t launch_stage_o8(const Patch& P, const Gauge& G, int periodic,
+                           int stage, int precision, hipStream_t st);
+inline hipError_t launch_stage(const Patch& P, const Gauge& G, int order,
+                               int periodic, int stage, int precision,
+                               hipStream_t st) {
+  return order == 8 ? launch_stage_o8(P, G, periodic, stage, precision, st)
+                    : launch_stage_o4(P, G, periodic, stage, precision, st);
+}
+
+// Constraint fields and norms (see bssn_constraints in bssn.h).
+struct ConstraintArgs {
+  const double* u;
+  double* H;
+  double* M;
+  double* Gc;
+  int32_t n[3];
+  int32_t ghost;
+  int32_t sy, sz;
+  int64_t sf;
+  double origin[3];
+  double h[3];
+  int32_t periodic;
+  int32_t ncent;
+  double centres[16][3];
+  double r_exc;
+};
+hipError_t launch_constraints(const ConstraintArgs& A, int order,
+                              double* partials, int nblocks_max,
+                              double* norms, hipStream_t st);
+int constraint_blocks(const ConstraintArgs& A);
+
+// Count of tiles whose minimum lapse is below thr (device counter).
+hipError_t launch_tile_count(const Patch& P, double thr,
+                             unsigned long long* counter, hipStream_t st);
+void tile_grid(const Patch& P, dim3& grd, dim3& blk);
+
+}  // namespace bssn

@@ -1,0 +1,242 @@
+// bssn_stage.h -- fused BSSN right-hand side + classical RK4 stage kernels.
+//
+// One thread per interior point; a workgroup covers a BX x BY tile of one
+// z-plane.  Stencil values are read straight from HBM through the vector L1
+// and L2 caches with raw buffer loads: each slot gets a buffer resource based
+// at the slot start, the lane's offset is the byte offset of the stencil's
+// lowest corner (x-R, y-R, z-R) and every tap adds a non-negative
+// compile-time multiple of the row/plane pitch in the scalar offset, so no
+// per-tap vector address arithmetic is issued.  Offsets beyond the buffer
+// read as zero instead of faulting.  Periodic grids wrap the indices per lane
+// (small grids only).
+//
+// The RK4 epilogue is fused: the stage's k never goes to memory.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "bssn_internal.h"
+#include "bssn_point.h"
+
+namespace bssn {
+
+constexpr int32_t kRsrcWord3 = 0x00020000;  // gfx9 raw 32-bit buffer
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const double* base,
+                                                       int32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, bytes,
+                                           kRsrcWord3);
+}
+
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r,
+                                        uint32_t voff, uint32_t soff) {
+  auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+  return __builtin_bit_cast(double, v);
+}
+
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                       double x) {
+  __builtin_amdgcn_raw_buffer_store_b64(
+      __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(
+                             r, 0, 0, 0)),
+                         x),
+      r, (int)voff, 0, 0);
+}
+
+// Static boundary: offsets relative to the stencil's lowest corner.
+template <int R>
+struct LdStatic {
+  const double* u;
+  int64_t sf;
+  int32_t nbytes;     // bytes of one slot (buffer range)
+  uint32_t vlo;       // byte offset of (x-R, y-R, z-R) within a slot
+  uint32_t str[3];    // bytes per step along x, y, z
+  __device__ __forceinline__ double at(int s, uint32_t soff) const {
+    return bload(rsrc(u + s * sf, nbytes), vlo, soff);
+  }
+  __device__ __forceinline__ double c(int s) const {
+    return at(s, R * (str[0] + str[1] + str[2]));
+  }
+  __device__ __forceinline__ double ax(int s, int a, int k) const {
+    return at(s, R * (str[0] + str[1] + str[2]) + k * (int)str[a]);
+  }
+  __device__ __forceinline__ double pl(int s, int a, int i, int b,
+                                       int j) const {
+    return at(s, R * (str[0] + str[1] + str[2]) + i * (int)str[a] +
+                     j * (int)str[b]);
+  }
+};
+
+// Periodic boundary: per-lane wrapped offsets for every reach.
+template <int R>
+struct LdPeriodic {
+  const double* u;
+  int64_t sf;
+  int32_t nbytes;
+  uint32_t o[3][2 * R + 1];  // byte offset contribution of axis a at k
+  __device__ __forceinline__ double at(int s, uint32_t v) const {
+    return bload(rsrc(u + s * sf, nbytes), v, 0);
+  }
+  __device__ __forceinline__ double c(int s) const {
+    return at(s, o[0][R] + o[1][R] + o[2][R]);
+  }
+  __device__ __forceinline__ double ax(int s, int a, int k) const {
+    uint32_t v = o[0][R] + o[1][R] + o[2][R];
+    v += o[a][R + k] - o[a][R];
+    return at(s, v);
+  }
+  __device__ __forceinline__ double pl(int s, int a, int i, int b,
+                                       int j) const {
+    const int cidx = 3 - a - b;
+    return at(s, o[a][R + i] + o[b][R + j] + o[cidx][R]);
+  }
+};
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Minimum lapse over the workgroup's points: the mixed-precision routing
+// predicate, identical in the FP32 and the FP64 kernel of a pair.
+__device__ __forceinline__ bool tile_needs_fp64(const Patch& P, bool active,
+                                                uint32_t vc, int32_t nbytes,
+                                                double thr) {
+  __shared__ double wmin[16];
+  double a = 1.0e300;
+  if (active) a = bload(rsrc(P.u_s + ALP * P.sf, nbytes), vc, 0);
+  a = wave_min(a);
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+  if ((tid & 63) == 0) wmin[tid >> 6] = a;
+  __syncthreads();
+  double m = wmin[0];
+  for (int w = 1; w < nw; ++w) m = fmin(m, wmin[w]);
+  return m < thr;
+}
+
+// Stage epilogue: k -> acc / out (FP64).
+template <typename T>
+__device__ __forceinline__ void epilogue(const Patch& P, int stage,
+                                         const T (&r)[NSLOT], uint32_t vc,
+                                         int32_t nbytes) {
+  const double dt = P.dt;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const double k = double(r[s]);
+    auto ro = rsrc(P.out + s * P.sf, nbytes);
+    if (stage == ST_RHS) {
+      bstore(ro, vc, k);
+      continue;
+    }
+    auto ra = rsrc(P.acc + s * P.sf, nbytes);
+    if (stage == ST_3) {
+      const double a = bload(ra, vc, 0);
+      bstore(ro, vc, a + (dt / 6.0) * k);
+    } else {
+      const double un = bload(rsrc(P.u_n + s * P.sf, nbytes), vc, 0);
+      if (stage == ST_0) {
+        bstore(ra, vc, un + (dt / 6.0) * k);
+        bstore(ro, vc, un + (dt / 2.0) * k);
+      } else {
+        const double a = bload(ra, vc, 0);
+        bstore(ra, vc, a + (dt / 3.0) * k);
+        bstore(ro, vc, un + (stage == ST_1 ? dt / 2.0 : dt) * k);
+      }
+    }
+  }
+}
+
+// One point of one patch: everything above, for the thread's point.
+template <int ORDER, bool PERIODIC, typename T>
+__device__ __forceinline__ void stage_point(const Patch& P, const Gauge& G,
+                                            int stage, int x, int y, int z) {
+  constexpr int R = FD<ORDER>::R;
+  const int g = P.ghost;
+  const int32_t nbytes = int32_t(P.sf * 8);
+  const uint32_t sy8 = uint32_t(P.sy) * 8u, sz8 = uint32_t(P.sz) * 8u;
+  const uint32_t vc =
+      uint32_t(z + g) * sz8 + uint32_t(y + g) * sy8 + uint32_t(x + g) * 8u;
+  const double ihd[3] = {1.0 / P.h[0], 1.0 / P.h[1], 1.0 / P.h[2]};
+  const double xc = P.origin[0] + x * P.h[0];
+  const double yc = P.origin[1] + y * P.h[1];
+  const double zc = P.origin[2] + z * P.h[2];
+  T r[NSLOT];
+  if constexpr (!PERIODIC) {
+    LdStatic<R> ld;
+    ld.u = P.u_s;
+    ld.sf = P.sf;
+    ld.nbytes = nbytes;
+    ld.vlo = vc - uint32_t(R) * (8u + sy8 + sz8);
+    ld.str[0] = 8u;
+    ld.str[1] = sy8;
+    ld.str[2] = sz8;
+    point_rhs<ORDER, T>(ld, ihd, xc, yc, zc, G, r);
+  } else {
+    LdPeriodic<R> ld;
+    ld.u = P.u_s;
+    ld.sf = P.sf;
+    ld.nbytes = nbytes;
+    const int pos[3] = {x, y, z};
+    const uint32_t st[3] = {8u, sy8, sz8};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int k = -R; k <= R; ++k) {
+        int q = pos[a] + k;
+        q = q < 0 ? q + P.n[a] : (q >= P.n[a] ? q - P.n[a] : q);
+        ld.o[a][R + k] = uint32_t(q + g) * st[a];
+      }
+    point_rhs<ORDER, T>(ld, ihd, xc, yc, zc, G, r);
+  }
+  epilogue<T>(P, stage, r, vc, nbytes);
+}
+
+template <int ORDER, bool PERIODIC, int TILES>
+__global__ void __launch_bounds__(256)
+    k_stage(const Patch P, const Gauge G, const int stage) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  const bool active = x < P.n[0] && y < P.n[1];
+  if constexpr (TILES != TILE_ALL) {
+    const int g = P.ghost;
+    const uint32_t vc = uint32_t(z + g) * uint32_t(P.sz) * 8u +
+                        uint32_t(y + g) * uint32_t(P.sy) * 8u +
+                        uint32_t(x + g) * 8u;
+    const bool f64 =
+        tile_needs_fp64(P, active, vc, int32_t(P.sf * 8), G.alpha_thr);
+    if (f64 != (TILES == TILE_FP64)) return;
+  }
+  if (!active) return;
+  if constexpr (TILES == TILE_FP32)
+    stage_point<ORDER, PERIODIC, float>(P, G, stage, x, y, z);
+  else
+    stage_point<ORDER, PERIODIC, double>(P, G, stage, x, y, z);
+}
+
+// ---- host-side launch -------------------------------------------------------------
+inline void stage_tile_shape(const Patch& P, dim3& blk) {
+  const int bx = P.n[0] > 32 ? 64 : 32;
+  blk = dim3(bx, 256 / bx, 1);
+}
+
+template <int ORDER, bool PERIODIC>
+hipError_t launch_stage_variant(const Patch& P, const Gauge& G, int stage,
+                                int precision, hipStream_t st) {
+  dim3 blk;
+  stage_tile_shape(P, blk);
+  dim3 grd((P.n[0] + blk.x - 1) / blk.x, (P.n[1] + blk.y - 1) / blk.y, P.n[2]);
+  if (precision == 0) {
+    hipLaunchKernelGGL((k_stage<ORDER, PERIODIC, TILE_ALL>), grd, blk, 0, st,
+                       P, G, stage);
+  } else {
+    hipLaunchKernelGGL((k_stage<ORDER, PERIODIC, TILE_FP32>), grd, blk, 0, st,
+                       P, G, stage);
+    hipLaunchKernelGGL((k_stage<ORDER, PERIODIC, TILE_FP64>), grd, blk, 0, st,
+                       P, G, stage);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace bssn

@@ -1,0 +1,108 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point include/bssn.h declares, and rejects invalid arguments before any HIP
+call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1111_3344_amd import bssn as B
+from paper_1111_3344_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bssn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for n in ("bssn_rhs", "rk4_stage", "bssn_constraints", "batch_patches",
+              "batch_patches_plan", "batch_patches_destroy",
+              "bssn_abi_version", "bssn_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    for n in _declared():
+        assert hasattr(L, n), f"{n} declared in bssn.h but not exported"
+    assert B.bssn_abi_version() == 1
+
+
+def _grid(**kw):
+    g = I.cell_centred(8, -1, 1, 3)
+    return B.c_grid(g), g
+
+
+P = ctypes.c_void_p
+
+
+def _stage(grid, prm, stage=0, dt=0.1, un=1, us=1, acc=2, out=3):
+    return B.lib().rk4_stage(ctypes.byref(grid), ctypes.byref(prm), stage,
+                             dt, P(un), P(us), P(acc), P(out), None)
+
+
+def test_validation_rejects_before_launch():
+    cg, g = _grid()
+    prm = B.Params().c()
+    # fake non-NULL device addresses: validation must fail before any use
+    assert _stage(cg, prm, stage=4) == B.BSSN_EINVAL
+    assert "stage" in B.bssn_last_error()
+    assert _stage(cg, prm, dt=float("nan")) == B.BSSN_EINVAL
+    assert _stage(cg, prm, un=0) == B.BSSN_EINVAL
+    assert _stage(cg, prm, out=1, us=1, un=5) == B.BSSN_EINVAL  # u_out == u_s
+    assert _stage(cg, prm, acc=1) == B.BSSN_EINVAL             # acc == u_n
+    assert _stage(cg, prm, stage=1, out=1, us=7) == B.BSSN_EINVAL
+    bad = B.c_grid(g)
+    bad.ghost = 2
+    assert _stage(bad, prm) == B.BSSN_EINVAL
+    assert "ghost" in B.bssn_last_error()
+    bad = B.c_grid(g)
+    bad.sy = 4
+    assert _stage(bad, prm) == B.BSSN_EINVAL
+    bad = B.c_grid(g)
+    bad.h[1] = 0.0
+    assert _stage(bad, prm) == B.BSSN_EINVAL
+    bad = B.c_grid(g)
+    bad.bc = 7
+    assert _stage(bad, prm) == B.BSSN_EINVAL
+    p8 = B.Params(fd_order=8).c()
+    assert _stage(cg, p8) == B.BSSN_EINVAL          # ghost 3 < 5
+    p6 = B.Params(fd_order=6).c()
+    assert _stage(cg, p6) == B.BSSN_EINVAL
+    pp = B.Params(precision=3).c()
+    assert _stage(cg, pp) == B.BSSN_EINVAL
+    pk = B.Params(ko_eps=-1.0).c()
+    assert _stage(cg, pk) == B.BSSN_EINVAL
+    assert B.lib().bssn_rhs(ctypes.byref(cg), ctypes.byref(prm), P(1), P(1),
+                            None) == B.BSSN_EINVAL
+    assert B.lib().rk4_stage(None, ctypes.byref(prm), 0, 0.1, P(1), P(1),
+                             P(2), P(3), None) == B.BSSN_EINVAL
+
+
+def test_constraints_validation():
+    cg, g = _grid()
+    prm = B.Params().c()
+    c = (ctypes.c_double * 3)(0, 0, 0)
+    L = B.lib()
+    assert L.bssn_constraints(ctypes.byref(cg), ctypes.byref(prm), P(1), None,
+                              None, None, c, 17, 0.0, P(2),
+                              None) == B.BSSN_EINVAL
+    assert L.bssn_constraints(ctypes.byref(cg), ctypes.byref(prm), P(1), None,
+                              None, None, c, 0, 0.0, None,
+                              None) == B.BSSN_EINVAL
+    assert L.bssn_constraints(ctypes.byref(cg), ctypes.byref(prm), P(1), P(1),
+                              None, None, c, 0, 0.0, P(2),
+                              None) == B.BSSN_EINVAL
+
+
+def test_periodic_grid_must_cover_stencil():
+    g = I.GridSpec((2, 8, 8), 3, (0.1,) * 3, (0,) * 3, I.BC_PERIODIC)
+    assert _stage(B.c_grid(g), B.Params().c()) == B.BSSN_EINVAL
