@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--path", default="auto", choices=["auto", "direct"],
+                    help="kernel: LDS-pipelined (auto) or direct-load")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for "
@@ -141,6 +143,8 @@ def main():
     import torch
     from paper_1111_3344_amd import bssn as B
 
+    B.bssn_set_path(B.BSSN_PATH_DIRECT if args.path == "direct"
+                    else B.BSSN_PATH_AUTO)
     g, u, order, dt, desc = build_state(args.workload)
     N = g.npoints
     res = {}

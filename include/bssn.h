@@ -77,7 +77,7 @@ typedef struct {
   int32_t ghost;      /* ghost layers per face: >= 3 (order 4), >= 5 (8)     */
   int64_t sy, sz, sf; /* element strides of a y-row, a z-plane, a slot;
                          sy >= n[0]+2g, sz >= sy*(n[1]+2g), sf >= sz*(n[2]+2g)
-                         and 25*sf < 2^31                                     */
+                         and 8*sf < 2^31 (one slot below 2 GiB)               */
   double origin[3];   /* coordinate of interior point (0,0,0)                */
   double h[3];        /* grid spacing, > 0                                    */
   int32_t bc;         /* BSSN_BC_STATIC or BSSN_BC_PERIODIC                  */
@@ -106,6 +106,19 @@ typedef struct {
 
 /* Version of this header the library was built from (BSSN_ABI_VERSION). */
 int bssn_abi_version(void);
+
+/* Kernel selection for bssn_rhs / rk4_stage (process-wide; results agree to
+ * rounding, both are checked against the same reference):
+ *   BSSN_PATH_AUTO    persistent kernel that stages every slot's stencil box
+ *                     in LDS through buffer->LDS DMA, for static grids whose
+ *                     layout gives 16-byte aligned rows (even strides and
+ *                     ptr + ghost - R - 1 aligned, R = 3 or 5); the
+ *                     direct-load kernel otherwise;
+ *   BSSN_PATH_DIRECT  always the direct-load kernel (one thread per point,
+ *                     stencil taps read through the caches).
+ * Errors: BSSN_EINVAL for other values. */
+enum { BSSN_PATH_AUTO = 0, BSSN_PATH_DIRECT = 1 };
+int bssn_set_path(int path);
 
 /* Message of the last failed call on this host thread; host memory owned by
  * the library, valid until the next call on this thread; never NULL. */

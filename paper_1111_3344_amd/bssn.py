@@ -22,6 +22,7 @@ BSSN_OK, BSSN_EINVAL, BSSN_ENOMEM, BSSN_EHIP, BSSN_ESTALE, \
     BSSN_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 BSSN_FP64, BSSN_MIXED = 0, 1
 BSSN_BC_STATIC, BSSN_BC_PERIODIC = 0, 1
+BSSN_PATH_AUTO, BSSN_PATH_DIRECT = 0, 1
 
 
 class BssnError(RuntimeError):
@@ -84,6 +85,7 @@ def lib():
         g, p = P(bssn_grid), P(bssn_params)
         L.bssn_abi_version.restype = ctypes.c_int
         L.bssn_last_error.restype = ctypes.c_char_p
+        L.bssn_set_path.argtypes = [ctypes.c_int]
         L.bssn_rhs.argtypes = [g, p, vp, vp, vp]
         L.rk4_stage.argtypes = [g, p, ctypes.c_int, ctypes.c_double, vp, vp,
                                 vp, vp, vp]
@@ -150,6 +152,10 @@ def _check(rc):
 
 def bssn_abi_version():
     return lib().bssn_abi_version()
+
+
+def bssn_set_path(path):
+    _check(lib().bssn_set_path(int(path)))
 
 
 def bssn_last_error():

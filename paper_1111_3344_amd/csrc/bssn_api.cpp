@@ -98,6 +98,24 @@ Patch make_patch(const bssn_grid* g) {
   return P;
 }
 
+static int g_path = PATH_AUTO;
+int stage_path() { return g_path; }
+
+int persistent_groups() {
+  static thread_local int cached_dev = -1, cached_n = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (dev != cached_dev) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount,
+                              dev) != hipSuccess || n <= 0)
+      n = 256;
+    cached_dev = dev;
+    cached_n = n;
+  }
+  return cached_n;
+}
+
 Gauge make_gauge(const bssn_params* p) {
   Gauge G{};
   G.ko_eps = p->ko_eps;
@@ -118,6 +136,13 @@ using namespace bssn;
 extern "C" {
 
 int bssn_abi_version(void) { return BSSN_ABI_VERSION; }
+
+int bssn_set_path(int path) {
+  if (path != BSSN_PATH_AUTO && path != BSSN_PATH_DIRECT)
+    return fail(BSSN_EINVAL, "path = %d is not a BSSN_PATH_* value", path);
+  g_path = path;
+  return BSSN_OK;
+}
 
 const char* bssn_last_error(void) { return g_err.c_str(); }
 

@@ -8,15 +8,25 @@ namespace bssn {
 
 // One RK4 stage (or the bare RHS for stage ST_RHS) on one patch.
 // precision 0: FP64; 1: FP32 tiles + FP64 tiles (two launches).
+// Kernel choice: PATH_AUTO uses the LDS-pipelined persistent kernel for
+// static grids whose layout allows 16-byte granules, the direct-load kernel
+// otherwise; PATH_DIRECT forces the direct-load kernel.
+enum : int { PATH_AUTO = 0, PATH_DIRECT = 1 };
 hipError_t launch_stage_o4(const Patch& P, const Gauge& G, int periodic,
-                           int stage, int precision, hipStream_t st);
+                           int stage, int precision, int path, int nwg,
+                           hipStream_t st);
 hipError_t launch_stage_o8(const Patch& P, const Gauge& G, int periodic,
-                           int stage, int precision, hipStream_t st);
+                           int stage, int precision, int path, int nwg,
+                           hipStream_t st);
+int stage_path();          // current PATH_* (bssn_set_path)
+int persistent_groups();   // workgroups of a persistent launch (CU count)
 inline hipError_t launch_stage(const Patch& P, const Gauge& G, int order,
                                int periodic, int stage, int precision,
                                hipStream_t st) {
-  return order == 8 ? launch_stage_o8(P, G, periodic, stage, precision, st)
-                    : launch_stage_o4(P, G, periodic, stage, precision, st);
+  const int path = stage_path(), nwg = persistent_groups();
+  return order == 8
+             ? launch_stage_o8(P, G, periodic, stage, precision, path, nwg, st)
+             : launch_stage_o4(P, G, periodic, stage, precision, path, nwg, st);
 }
 
 // Constraint fields and norms (see bssn_constraints in bssn.h).

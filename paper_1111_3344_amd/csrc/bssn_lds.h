@@ -1,0 +1,342 @@
+// bssn_lds.h -- the fused RHS + RK4 stage as a persistent kernel that
+// stages every slot's stencil box in LDS through the buffer->LDS DMA path.
+//
+// A workgroup of 256 threads owns one 16 x 4 x 4 tile at a time (one thread
+// per point, wave w = z-plane w of the tile).  The point function visits the
+// 25 slots one phase at a time (kPhaseSlot order); for each phase the haloed
+// box of that slot, (16 + 2R + 1) x (4 + 2R) x (4 + 2R) doubles with rows
+// starting one column early so that every 16-byte granule is aligned, sits
+// in one of NBUF LDS buffers.  Boxes are fetched with
+// buffer_load_dwordx4 ... lds (each lane moves one granule straight into
+// LDS, no registers), NBUF - 1 phases ahead of use, and the pipeline runs
+// on across tile boundaries, so the HBM/L2 latency of one phase hides behind
+// the arithmetic of the previous ones.  Stencil taps are then ds_read_b64
+// with immediate offsets from one per-thread address.
+//
+// Synchronisation per phase: wait until at most (NBUF-2)*L of this wave's
+// DMA instructions are outstanding (so the current phase's box has landed),
+// barrier (all waves' granules have landed, and every wave is done with the
+// previous phase's buffer), then issue the DMA for phase p + NBUF - 1 into
+// the buffer phase p - 1 used.  Buffers are distinct __shared__ arrays
+// selected by compile-time phase numbers.
+//
+// Tiles are walked persistently: workgroup b takes tiles in an order that
+// keeps the tiles in flight on one XCD (b mod 8) contiguous in x, so halos
+// shared by x-neighbours are hits in that XCD's L2.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "bssn_stage.h"
+
+namespace bssn {
+
+template <int ORDER>
+struct TileGeo;
+template <>
+struct TileGeo<4> {
+  static constexpr int R = 3, TX = 16, TY = 4, TZ = 4;
+  static constexpr int W = 24;  // (TX + 2R + 1) rounded up to even
+  static constexpr int H = TY + 2 * R, D = TZ + 2 * R;
+  static constexpr int G = W * H * D / 2;         // granules per box
+  static constexpr int L = (G + 255) / 256;       // DMA instructions per wave
+  static constexpr int NBUF = 5, NPH = 25;        // NPH % NBUF == 0
+  static constexpr int BUFD = L * 256 * 2;        // doubles per buffer
+};
+template <>
+struct TileGeo<8> {
+  static constexpr int R = 5, TX = 16, TY = 4, TZ = 4;
+  static constexpr int W = 28;
+  static constexpr int H = TY + 2 * R, D = TZ + 2 * R;
+  static constexpr int G = W * H * D / 2;
+  static constexpr int L = (G + 255) / 256;
+  static constexpr int NBUF = 3, NPH = 27;  // two idle phases per tile
+  static constexpr int BUFD = L * 256 * 2;
+};
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// LDS buffers of one workgroup.
+template <class Geo>
+struct LdsBufs {
+  double* b[Geo::NBUF];
+};
+
+// Per-lane DMA byte offsets (within one slot) of the granules this lane
+// moves for a tile at (x0, y0, z0) (interior coordinates).
+template <class Geo>
+__device__ __forceinline__ void dma_offsets(const Patch& P, int x0, int y0,
+                                            int z0, int wave, int lane,
+                                            uint32_t (&off)[Geo::L]) {
+  const int g = P.ghost;
+#pragma unroll
+  for (int j = 0; j < Geo::L; ++j) {
+    int q = (wave * Geo::L + j) * 64 + lane;
+    if (q >= Geo::G) q = 0;  // padding lanes reload granule 0 into the pad
+    const int col = q % (Geo::W / 2);
+    const int row = q / (Geo::W / 2);
+    const int yy = row % Geo::H, zz = row / Geo::H;
+    const int64_t e = int64_t(z0 + zz + g - Geo::R) * P.sz +
+                      int64_t(y0 + yy + g - Geo::R) * P.sy +
+                      (x0 + g - Geo::R - 1) + 2 * col;
+    off[j] = uint32_t(e * 8);  // < 0 wraps to a huge offset: reads 0
+  }
+}
+
+// Buffer resource of slot s built where it is used: the base goes through an
+// opaque scalar move so the 25 per-slot descriptors are not all hoisted out
+// of the tile loop (that would pin ~100 SGPRs).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slot_rsrc(const double* u,
+                                                            int64_t sf, int s,
+                                                            int32_t nbytes) {
+  const double* b = u;
+  asm volatile("" : "+s"(b));  // opaque here, so b + s*sf stays here too
+  return rsrc(b + s * sf, nbytes);
+}
+
+template <class Geo>
+__device__ __forceinline__ void dma_issue(const Patch& P, int slot,
+                                          double* buf, int wave,
+                                          const uint32_t (&off)[Geo::L]) {
+  const auto r = slot_rsrc(P.u_s, P.sf, slot, int32_t(P.sf * 8));
+#pragma unroll
+  for (int j = 0; j < Geo::L; ++j) {
+    lds_ptr_t dst = (lds_ptr_t)(buf + (wave * Geo::L + j) * 128);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 16, int(off[j]), 0, 0,
+                                             0);
+  }
+}
+
+// Loader used by point_rhs inside the pipelined kernel.
+template <class Geo>
+struct LdLds {
+  const Patch* P;
+  double* const* buf;      // NBUF buffers
+  const uint32_t* off_cur;  // this tile's DMA offsets
+  const uint32_t* off_nxt;  // next tile's
+  int wave;
+  int cidx;                // element index of the thread's centre in a box
+  uint32_t vc;             // byte offset of the thread's point in a slot
+  int32_t nbytes;
+  mutable const double* cur;
+
+  __device__ __forceinline__ double g(int s) const {
+    return bload(slot_rsrc(P->u_s, P->sf, s, nbytes), vc, 0);
+  }
+  __device__ __forceinline__ void enter(int s) const {
+    const int p = phase_of(s);
+    phase(p);
+    cur = buf[p % Geo::NBUF];
+  }
+  // one pipeline step at phase p (0 <= p < NPH)
+  __device__ __forceinline__ void phase(int p) const {
+    // at most (NBUF-2)*L newer DMA instructions than phase p's may be in
+    // flight: then phase p's box has landed for this wave
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"((Geo::NBUF - 2) * Geo::L)
+                 : "memory");
+    __builtin_amdgcn_s_barrier();
+    const int q = p + Geo::NBUF - 1;  // phase to prefetch
+    double* dst = buf[q % Geo::NBUF];
+    if (q < Geo::NPH) {
+      if (q < NSLOT) {
+        uint32_t o[Geo::L];
+#pragma unroll
+        for (int j = 0; j < Geo::L; ++j) o[j] = off_cur[j];
+        dma_issue<Geo>(*P, kPhaseSlot[q], dst, wave, o);
+      } else {
+        uint32_t o[Geo::L];
+#pragma unroll
+        for (int j = 0; j < Geo::L; ++j) o[j] = off_cur[j];
+        dma_issue<Geo>(*P, kPhaseSlot[0], dst, wave, o);  // idle phase
+      }
+    } else {
+      const int qn = q - Geo::NPH;
+      uint32_t o[Geo::L];
+#pragma unroll
+      for (int j = 0; j < Geo::L; ++j) o[j] = off_nxt[j];
+      dma_issue<Geo>(*P, qn < NSLOT ? kPhaseSlot[qn] : kPhaseSlot[0], dst,
+                     wave, o);
+    }
+  }
+  __device__ __forceinline__ int str(int a) const {
+    return a == 0 ? 1 : (a == 1 ? Geo::W : Geo::W * Geo::H);
+  }
+  __device__ __forceinline__ double c(int) const { return cur[cidx]; }
+  __device__ __forceinline__ double ax(int, int a, int k) const {
+    return cur[cidx + k * str(a)];
+  }
+  __device__ __forceinline__ double pl(int, int a, int i, int b, int j) const {
+    return cur[cidx + i * str(a) + j * str(b)];
+  }
+};
+
+// tile t (linear, x fastest) -> interior coordinates of its origin
+struct TileMap {
+  int ntx, nty, ntz, ntiles;
+};
+
+// Position of workgroup wg in the tile walk (XCD-aware): workgroups are
+// dispatched to the 8 XCDs round-robin, so wg, wg+8, ... share an XCD; they
+// get consecutive positions, hence neighbouring tiles.
+__host__ __device__ __forceinline__ int walk_pos(int wg, int nwg) {
+  return (nwg & 7) == 0 ? (wg & 7) * (nwg >> 3) + (wg >> 3) : wg;
+}
+// k-th tile of the workgroup at walk position lin
+__host__ __device__ __forceinline__ int tile_of(int lin, int nwg, int k) {
+  return k * nwg + lin;
+}
+// number of tiles the workgroup at walk position lin processes
+__host__ __device__ __forceinline__ int tiles_of(int lin, int nwg,
+                                                 int ntiles) {
+  return ntiles > lin ? (ntiles - 1 - lin) / nwg + 1 : 0;
+}
+
+// MIXED = false: FP64 everywhere.  MIXED = true: per tile, FP32 stencils and
+// algebra unless the tile's minimum lapse is below G.alpha_thr (then FP64);
+// the branch is uniform over the workgroup.
+template <int ORDER, bool MIXED>
+__global__ void __launch_bounds__(256)
+    k_stage_lds(const Patch P, const Gauge G, const int stage,
+                const TileMap M) {
+  using Geo = TileGeo<ORDER>;
+  __shared__ __attribute__((aligned(16))) double s0[Geo::BUFD];
+  __shared__ __attribute__((aligned(16))) double s1[Geo::BUFD];
+  __shared__ __attribute__((aligned(16))) double s2[Geo::BUFD];
+  __shared__ __attribute__((aligned(16))) double s3[Geo::NBUF > 3 ? Geo::BUFD : 2];
+  __shared__ __attribute__((aligned(16))) double s4[Geo::NBUF > 4 ? Geo::BUFD : 2];
+  double* bufs[5] = {s0, s1, s2, s3, s4};
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int tx = lane & 15, ty = lane >> 4, tz = wave;
+  const int nwg = gridDim.x;
+  const int lin = walk_pos(blockIdx.x, nwg);
+  const int ntile_mine = tiles_of(lin, nwg, M.ntiles);
+  if (ntile_mine == 0) return;
+
+  auto origin = [&](int t, int& x0, int& y0, int& z0) {
+    const int ix = t % M.ntx, iy = (t / M.ntx) % M.nty, iz = t / (M.ntx * M.nty);
+    x0 = ix * Geo::TX;
+    y0 = iy * Geo::TY;
+    z0 = iz * Geo::TZ;
+  };
+  uint32_t offA[Geo::L], offB[Geo::L];
+  int x0, y0, z0;
+  {
+    const int t0 = tile_of(lin, nwg, 0);
+    origin(t0, x0, y0, z0);
+    dma_offsets<Geo>(P, x0, y0, z0, wave, lane, offA);
+    int xn, yn, zn;
+    const int t1 = ntile_mine > 1 ? tile_of(lin, nwg, 1) : t0;
+    origin(t1, xn, yn, zn);
+    dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
+  }
+  // prologue: phases 0 .. NBUF-2 of the first tile
+#pragma unroll
+  for (int q = 0; q < Geo::NBUF - 1; ++q)
+    dma_issue<Geo>(P, kPhaseSlot[q], bufs[q], wave, offA);
+
+  const double ihd[3] = {1.0 / P.h[0], 1.0 / P.h[1], 1.0 / P.h[2]};
+  const int32_t nbytes = int32_t(P.sf * 8);
+  const uint32_t sy8 = uint32_t(P.sy) * 8u, sz8 = uint32_t(P.sz) * 8u;
+  for (int k = 0; k < ntile_mine; ++k) {
+    const int t = tile_of(lin, nwg, k);
+    origin(t, x0, y0, z0);
+    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+    const bool active = x < P.n[0] && y < P.n[1] && z < P.n[2];
+    const int g = P.ghost;
+    LdLds<Geo> ld;
+    ld.P = &P;
+    ld.buf = bufs;
+    ld.off_cur = offA;
+    ld.off_nxt = offB;
+    ld.wave = wave;
+    ld.cidx = ((tz + Geo::R) * Geo::H + (ty + Geo::R)) * Geo::W + tx +
+              Geo::R + 1;
+    ld.vc = active ? uint32_t(z + g) * sz8 + uint32_t(y + g) * sy8 +
+                         uint32_t(x + g) * 8u
+                   : 0u;
+    ld.nbytes = nbytes;
+    const double xc = P.origin[0] + x * P.h[0];
+    const double yc = P.origin[1] + y * P.h[1];
+    const double zc = P.origin[2] + z * P.h[2];
+    bool f64 = true;
+    if constexpr (MIXED) {
+      __shared__ double wmin[4];
+      double a = active ? ld.g(ALP) : 1.0e300;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1)
+        a = fmin(a, __shfl_xor(a, off, 64));
+      if (lane == 0) wmin[wave] = a;
+      __builtin_amdgcn_s_barrier();
+      const double m = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+      f64 = m < G.alpha_thr;
+      __builtin_amdgcn_s_barrier();  // wmin is reused by the next tile
+    }
+    if (f64) {
+      double r[NSLOT];
+      point_rhs<ORDER, double>(ld, ihd, xc, yc, zc, G, r);
+#pragma unroll
+      for (int p = NSLOT; p < Geo::NPH; ++p) ld.phase(p);  // idle phases
+      if (active) epilogue<double>(P, stage, r, ld.vc, nbytes);
+    } else {
+      float r[NSLOT];
+      point_rhs<ORDER, float>(ld, ihd, xc, yc, zc, G, r);
+#pragma unroll
+      for (int p = NSLOT; p < Geo::NPH; ++p) ld.phase(p);
+      if (active) epilogue<float>(P, stage, r, ld.vc, nbytes);
+    }
+    // next tile: its offsets become current, prepare the one after
+#pragma unroll
+    for (int j = 0; j < Geo::L; ++j) offA[j] = offB[j];
+    if (k + 2 < ntile_mine) {
+      int xn, yn, zn;
+      origin(tile_of(lin, nwg, k + 2), xn, yn, zn);
+      dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
+    }
+  }
+  // drain outstanding DMA before the workgroup retires
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+template <int ORDER>
+inline TileMap lds_tile_map(const Patch& P) {
+  using Geo = TileGeo<ORDER>;
+  TileMap M;
+  M.ntx = (P.n[0] + Geo::TX - 1) / Geo::TX;
+  M.nty = (P.n[1] + Geo::TY - 1) / Geo::TY;
+  M.ntz = (P.n[2] + Geo::TZ - 1) / Geo::TZ;
+  M.ntiles = M.ntx * M.nty * M.ntz;
+  return M;
+}
+
+// The LDS path needs 16-byte aligned granules: (u + ghost - R - 1) aligned
+// and even strides.
+template <int ORDER>
+inline bool lds_path_ok(const Patch& P) {
+  using Geo = TileGeo<ORDER>;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(P.u_s) +
+                      8u * uintptr_t(P.ghost - Geo::R - 1);
+  return (a % 16) == 0 && (P.sy % 2) == 0 && (P.sz % 2) == 0 &&
+         (P.sf % 2) == 0;
+}
+
+}  // namespace bssn
+
+namespace bssn {
+
+template <int ORDER>
+hipError_t launch_stage_lds(const Patch& P, const Gauge& G, int stage,
+                            int precision, int nwg_max, hipStream_t st) {
+  const TileMap M = lds_tile_map<ORDER>(P);
+  const int nwg = M.ntiles < nwg_max ? M.ntiles : nwg_max;
+  if (precision == 0)
+    hipLaunchKernelGGL((k_stage_lds<ORDER, false>), dim3(nwg), dim3(256), 0,
+                       st, P, G, stage, M);
+  else
+    hipLaunchKernelGGL((k_stage_lds<ORDER, true>), dim3(nwg), dim3(256), 0,
+                       st, P, G, stage, M);
+  return hipGetLastError();
+}
+
+}  // namespace bssn

@@ -115,9 +115,30 @@ struct FD<8> {
   }
 };
 
+// Order in which point_rhs visits the slots (one phase per slot).
+constexpr int kPhaseSlot[NSLOT] = {GXX,  GXY,  GXZ,  GYY,  GYZ,  GZZ, GAMX,
+                                   GAMY, GAMZ, PHI,  ALP,  TRK,  BETX, BETY,
+                                   BETZ, AXX,  AXY,  AXZ,  AYY,  AYZ,  AZZ,
+                                   BX,   BY,   BZ,   ADOT};
+// inverse of kPhaseSlot (non-recursive, so it folds after unrolling)
+__host__ __device__ constexpr int phase_of(int slot) {
+  return slot == PHI   ? 9
+         : slot <= GZZ ? slot - GXX
+         : slot == TRK ? 11
+         : slot <= AZZ ? 15 + (slot - AXX)
+         : slot <= GAMZ ? 6 + (slot - GAMX)
+         : slot == ALP ? 10
+         : slot <= BETZ ? 12 + (slot - BETX)
+         : slot <= BZ   ? 21 + (slot - BX)
+                        : 24;
+}
+
 // symmetric pair -> 0..5 (xx xy xz yy yz zz)
+__host__ __device__ constexpr int S_(int i, int j) {  // i <= j
+  return i == 0 ? j : (i == 1 ? 2 + j : 5);
+}
 __host__ __device__ constexpr int S(int i, int j) {
-  return i > j ? S(j, i) : (i == 0 ? j : (i == 1 ? 2 + j : 5));
+  return i <= j ? S_(i, j) : S_(j, i);
 }
 
 // ---- stencil helpers ----------------------------------------------------------
@@ -204,6 +225,10 @@ __device__ __forceinline__ float t_exp<float>(float x) {
 
 // ---- the right-hand side at one point --------------------------------------------
 // ih: 1/h per axis; (xc, yc, zc): coordinates of the point (for q(r)).
+// Loader interface: g(s) centre value of slot s (any slot, any time);
+// enter(s) starts the phase of slot s (slots are entered in the order of
+// kPhaseSlot); c(s), ax(s, a, k), pl(s, a, i, b, j) read slot s inside its
+// phase (centre, offset k along axis a, offsets i along a and j along b).
 template <int ORDER, typename T, class L>
 __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
                                           double xc, double yc, double zc,
@@ -220,12 +245,12 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
           ihyz = T(ihd[1] * ihd[2]);
 
   // centre values used by the algebra
-  const T phi = T(ld.c(PHI)), trK = T(ld.c(TRK)), alpha = T(ld.c(ALP));
+  const T phi = T(ld.g(PHI)), trK = T(ld.g(TRK)), alpha = T(ld.g(ALP));
   T gt[6], At[6];
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
-    gt[m] = T(ld.c(GXX + m));
-    At[m] = T(ld.c(AXX + m));
+    gt[m] = T(ld.g(GXX + m));
+    At[m] = T(ld.g(AXX + m));
   }
 
   // inverse conformal metric (adjugate / determinant)
@@ -241,29 +266,11 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
   gu[4] = (gt[1] * gt[2] - gt[0] * gt[4]) * idet;
   gu[5] = (gt[0] * gt[3] - gt[1] * gt[1]) * idet;
 
-  // A~^i_j and A~^ij
-  T Aud[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      Aud[i][j] = gu[S(i, 0)] * At[S(0, j)] + gu[S(i, 1)] * At[S(1, j)] +
-                  gu[S(i, 2)] * At[S(2, j)];
-  T Auu[6];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = i; j < 3; ++j)
-      Auu[S(i, j)] = Aud[i][0] * gu[S(0, j)] + Aud[i][1] * gu[S(1, j)] +
-                     Aud[i][2] * gu[S(2, j)];
-  const T AA = At[0] * Auu[0] + At[3] * Auu[3] + At[5] * Auu[5] +
-               T(2) * (At[1] * Auu[1] + At[2] * Auu[2] + At[4] * Auu[4]);
-
   // advection + dissipation weights per axis
   T cw[3][2 * R];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double bb = ld.c(BETX + a);
+    const double bb = ld.g(BETX + a);
     const bool pos = bb > 0.0;
 #pragma unroll
     for (int k = -R; k <= R; ++k) {
@@ -279,7 +286,7 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
     T d2[3];
-    BSSN_PHASE();
+    ld.enter(GXX + m);
     r[GXX + m] =
         star<ORDER, T, true, true>(ld, GXX + m, cw, ih, ih2, dgt[m], d2);
     BSSN_PHASE();
@@ -325,39 +332,33 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
     for (int i = 0; i < 3; ++i)
       Gd[i] = -(gu[S(i, 0)] * Q[0] + gu[S(i, 1)] * Q[1] + gu[S(i, 2)] * Q[2]);
   }
-  // quadratic Ricci terms:
+  // quadratic Ricci terms, one k at a time:
   //   gt^lm (G^k_li G_jkm + G^k_lj G_ikm + G^k_im G_klj)
-  //   = sum_km [ H3[k][m][i] Gl_jkm + H3[k][m][j] Gl_ikm + G^k_im H2[k][m][j] ]
-  // with H3[k][m][i] = gt^ml G^k_li and H2[k][m][j] = gt^ml G_klj, and
+  //   = sum_k sum_m [ H3_k[m][i] Gl_jkm + H3_k[m][j] Gl_ikm
+  //                  + G^k_im H2_k[m][j] ]
+  // with H3_k[m][i] = gt^ml G^k_li and H2_k[m][j] = gt^ml G_klj, and
   //   - (Gl_ijk + Gl_jik) Gd^k / 2
-  {
-    T H3[3][3][3], H2[3][3][3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < 3; ++k) {
+    T H3[3][3], H2[3][3];
 #pragma unroll
-      for (int m = 0; m < 3; ++m)
+    for (int m = 0; m < 3; ++m)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          H3[k][m][i] = gu[S(m, 0)] * Gu[k][S(0, i)] +
-                        gu[S(m, 1)] * Gu[k][S(1, i)] +
-                        gu[S(m, 2)] * Gu[k][S(2, i)];
-          H2[k][m][i] = gu[S(m, 0)] * Gl[k][S(0, i)] +
-                        gu[S(m, 1)] * Gl[k][S(1, i)] +
-                        gu[S(m, 2)] * Gl[k][S(2, i)];
-        }
+      for (int i = 0; i < 3; ++i) {
+        H3[m][i] = gu[S(m, 0)] * Gu[k][S(0, i)] + gu[S(m, 1)] * Gu[k][S(1, i)] +
+                   gu[S(m, 2)] * Gu[k][S(2, i)];
+        H2[m][i] = gu[S(m, 0)] * Gl[k][S(0, i)] + gu[S(m, 1)] * Gl[k][S(1, i)] +
+                   gu[S(m, 2)] * Gl[k][S(2, i)];
+      }
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = i; j < 3; ++j) {
-        T s = T(0);
+        T s = -T(0.5) * (Gl[i][S(j, k)] + Gl[j][S(i, k)]) * Gd[k];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          s -= T(0.5) * (Gl[i][S(j, k)] + Gl[j][S(i, k)]) * Gd[k];
-#pragma unroll
-          for (int m = 0; m < 3; ++m)
-            s += H3[k][m][i] * Gl[j][S(k, m)] + H3[k][m][j] * Gl[i][S(k, m)] +
-                 Gu[k][S(i, m)] * H2[k][m][j];
-        }
+        for (int m = 0; m < 3; ++m)
+          s += H3[m][i] * Gl[j][S(k, m)] + H3[m][j] * Gl[i][S(k, m)] +
+               Gu[k][S(i, m)] * H2[m][j];
         Rt[S(i, j)] += s;
         keep(Rt[S(i, j)]);
       }
@@ -367,7 +368,7 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     T dG[3];
-    BSSN_PHASE();
+    ld.enter(GAMX + k);
     r[GAMX + k] =
         star<ORDER, T, true, false>(ld, GAMX + k, cw, ih, ih2, dG, nullptr);
 #pragma unroll
@@ -381,7 +382,7 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
   T dphi[3];
   {
     T d2[3];
-    BSSN_PHASE();
+    ld.enter(PHI);
     r[PHI] = star<ORDER, T, true, true>(ld, PHI, cw, ih, ih2, dphi, d2);
     T dd[6];
     dd[0] = d2[0];
@@ -415,10 +416,27 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
 
   // ---- alpha: X_ij, the A~ and K sources, part of Gt's source ----
   const T em4phi = t_exp<T>(T(-4) * phi);
+  // A~^i_j, A~^ij and A~_ij A~^ij (only the alpha phase needs them)
+  T Aud[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Aud[i][j] = gu[S(i, 0)] * At[S(0, j)] + gu[S(i, 1)] * At[S(1, j)] +
+                  gu[S(i, 2)] * At[S(2, j)];
+  T Auu[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j)
+      Auu[S(i, j)] = Aud[i][0] * gu[S(0, j)] + Aud[i][1] * gu[S(1, j)] +
+                     Aud[i][2] * gu[S(2, j)];
+  const T AA = At[0] * Auu[0] + At[3] * Auu[3] + At[5] * Auu[5] +
+               T(2) * (At[1] * Auu[1] + At[2] * Auu[2] + At[4] * Auu[4]);
   T Tg[3];
   {
     T dalp[3], d2[3];
-    BSSN_PHASE();
+    ld.enter(ALP);
     r[ALP] = star<ORDER, T, true, true>(ld, ALP, cw, ih, ih2, dalp, d2);
     T dd[6];
     dd[0] = d2[0];
@@ -481,7 +499,7 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
   // ---- K ----
   {
     T dK[3];
-    BSSN_PHASE();
+    ld.enter(TRK);
     r[TRK] += star<ORDER, T, true, false>(ld, TRK, cw, ih, ih2, dK, nullptr);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -498,7 +516,7 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     T db[3], d2[3];
-    BSSN_PHASE();
+    ld.enter(BETX + k);
     r[BETX + k] =
         star<ORDER, T, true, true>(ld, BETX + k, cw, ih, ih2, db, d2);
     T dd[6];
@@ -538,18 +556,20 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
   // ---- advected-only parts: A~ (sources above), B, A ----
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
-    BSSN_PHASE();
+    ld.enter(AXX + m);
     r[AXX + m] +=
         star<ORDER, T, false, false>(ld, AXX + m, cw, ih, ih2, nullptr,
                                      nullptr);
   }
+  T Bv[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    BSSN_PHASE();
+    ld.enter(BX + i);
+    Bv[i] = T(ld.c(BX + i));
     r[BX + i] = star<ORDER, T, false, false>(ld, BX + i, cw, ih, ih2, nullptr,
                                              nullptr);
   }
-  BSSN_PHASE();
+  ld.enter(ADOT);
   r[ADOT] = star<ORDER, T, false, false>(ld, ADOT, cw, ih, ih2, nullptr,
                                          nullptr);
 
@@ -565,9 +585,8 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const T Bi = T(ld.c(BX + i));
-      r[BETX + i] += T(G.shift_G) * Bi;
-      r[BX + i] += Tg[i] - T(G.eta) * q * Bi;
+      r[BETX + i] += T(G.shift_G) * Bv[i];
+      r[BX + i] += Tg[i] - T(G.eta) * q * Bv[i];
     }
   }
 }

@@ -1,11 +1,15 @@
 // bssn_rhs_o8.hip -- order-8 instantiations of the stage kernels.
 #include "bssn_kernels.h"
+#include "bssn_lds.h"
 #include "bssn_stage.h"
 
 namespace bssn {
 
 hipError_t launch_stage_o8(const Patch& P, const Gauge& G, int periodic,
-                           int stage, int precision, hipStream_t st) {
+                           int stage, int precision, int path, int nwg,
+                           hipStream_t st) {
+  const bool lds = !periodic && path != PATH_DIRECT && lds_path_ok<8>(P);
+  if (lds) return launch_stage_lds<8>(P, G, stage, precision, nwg, st);
   return periodic
              ? launch_stage_variant<8, true>(P, G, stage, precision, st)
              : launch_stage_variant<8, false>(P, G, stage, precision, st);

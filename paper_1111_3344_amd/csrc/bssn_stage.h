@@ -53,6 +53,8 @@ struct LdStatic {
   __device__ __forceinline__ double at(int s, uint32_t soff) const {
     return bload(rsrc(u + s * sf, nbytes), vlo, soff);
   }
+  __device__ __forceinline__ void enter(int) const { BSSN_PHASE(); }
+  __device__ __forceinline__ double g(int s) const { return c(s); }
   __device__ __forceinline__ double c(int s) const {
     return at(s, R * (str[0] + str[1] + str[2]));
   }
@@ -76,6 +78,8 @@ struct LdPeriodic {
   __device__ __forceinline__ double at(int s, uint32_t v) const {
     return bload(rsrc(u + s * sf, nbytes), v, 0);
   }
+  __device__ __forceinline__ void enter(int) const { BSSN_PHASE(); }
+  __device__ __forceinline__ double g(int s) const { return c(s); }
   __device__ __forceinline__ double c(int s) const {
     return at(s, o[0][R] + o[1][R] + o[2][R]);
   }

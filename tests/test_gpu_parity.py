@@ -113,13 +113,23 @@ CASES = {
 }
 
 
+@pytest.fixture(params=["auto", "direct"])
+def path(request, B):
+    """Both kernels: the LDS-pipelined one (auto on static grids) and the
+    direct-load one."""
+    B.bssn_set_path(B.BSSN_PATH_AUTO if request.param == "auto"
+                    else B.BSSN_PATH_DIRECT)
+    yield request.param
+    B.bssn_set_path(B.BSSN_PATH_AUTO)
+
+
 @pytest.mark.parametrize("case", list(CASES))
-def test_rhs_matches_oracle(B, case):
+def test_rhs_matches_oracle(B, case, path):
     gfn, dfn, kw = CASES[case]
     g = gfn()
     u = dfn(g)
     prm = B.Params(**kw)
-    print(f"[rhs] {case} n={g.n}", flush=True)
+    print(f"[rhs] {case} n={g.n} path={path}", flush=True)
     ref = O.rhs(g, oparams(prm), u)
     got = gpu_rhs(B, g, prm, u)
     e = rhs_err(g, got, ref)
@@ -138,12 +148,12 @@ def test_rhs_matches_oracle(B, case):
     ("smooth-periodic", 2, 0.02),
     ("bl-two-punctures-48", 2, 0.1),
     ("order8-smooth-static", 1, 0.02)])
-def test_rk4_steps_match_oracle(B, case, nsteps, dt):
+def test_rk4_steps_match_oracle(B, case, nsteps, dt, path):
     gfn, dfn, kw = CASES[case]
     g = gfn()
     u0 = dfn(g)
     prm = B.Params(**kw)
-    print(f"[rk4] {case} n={g.n} steps={nsteps}", flush=True)
+    print(f"[rk4] {case} n={g.n} steps={nsteps} path={path}", flush=True)
     ref = O.rk4_steps(g, oparams(prm), dt, u0, nsteps)
     got = gpu_steps(B, g, prm, dt, u0, nsteps)
     tol = state_tol(g, u0, ref, nsteps)
@@ -156,7 +166,7 @@ def test_rk4_steps_match_oracle(B, case, nsteps, dt):
         assert np.array_equal(g.view(got)[:, mask], g.view(u0)[:, mask])
 
 
-def test_minkowski_rhs_is_exactly_zero(B):
+def test_minkowski_rhs_is_exactly_zero(B, path):
     for prec in (B.BSSN_FP64, B.BSSN_MIXED):
         for order, gh in ((4, 3), (8, 5)):
             g = I.GridSpec((40, 9, 7), gh, (0.1,) * 3, (0.0,) * 3,
@@ -177,7 +187,7 @@ def test_periodic_translation_invariance_bitwise(B):
                                   np.roll(g.interior(r1), (1, 2), axis=(1, 3)))
 
 
-def test_runs_are_bitwise_reproducible(B):
+def test_runs_are_bitwise_reproducible(B, path):
     g = I.GridSpec((70, 38, 29), 3, (0.11, 0.13, 0.12), (-3.8, -2.4, -1.7),
                    I.BC_STATIC)
     u = I.smooth_random(g, seed=7)
@@ -212,7 +222,7 @@ def _sample_points(g, n=400, seed=0):
 
 
 @pytest.mark.parametrize("case", list(FULL))
-def test_full_size_stage0_sampled(B, case):
+def test_full_size_stage0_sampled(B, case, path):
     """At the benchmark sizes, stage 0 of RK4 (same launch as the
     benchmark) against the oracle evaluated point by point."""
     gfn, dfn, order = FULL[case]
