@@ -91,6 +91,13 @@ Patch make_patch(const bssn_grid* g) {
     P.origin[a] = g->origin[a];
     P.h[a] = g->h[a];
   }
+  for (int a = 0; a < 3; ++a) {
+    P.ih[a] = 1.0 / g->h[a];
+    P.ih2[a] = 1.0 / (g->h[a] * g->h[a]);
+  }
+  P.ihm[0] = 1.0 / (g->h[0] * g->h[1]);
+  P.ihm[1] = 1.0 / (g->h[0] * g->h[2]);
+  P.ihm[2] = 1.0 / (g->h[1] * g->h[2]);
   P.ghost = g->ghost;
   P.sy = int32_t(g->sy);
   P.sz = int32_t(g->sz);

@@ -34,6 +34,9 @@ struct Patch {
   double origin[3];
   double h[3];
   double dt;
+  // uniform inverse spacings, computed on the host so they stay in SGPRs:
+  // 1/h_a, 1/h_a^2, and 1/(h_x h_y), 1/(h_x h_z), 1/(h_y h_z)
+  double ih[3], ih2[3], ihm[3];
 };
 
 struct Gauge {

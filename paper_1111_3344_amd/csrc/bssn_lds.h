@@ -54,6 +54,7 @@ struct TileGeo<8> {
 };
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(3))) double lds_double;
 
 // LDS buffers of one workgroup.
 template <class Geo>
@@ -93,79 +94,171 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t slot_rsrc(const double* u,
   return rsrc(b + s * sf, nbytes);
 }
 
+// One buffer->LDS DMA instruction: every lane moves the 16 bytes at
+// `voff` of the buffer described by (base, nbytes) to LDS address
+// lds + 16 * lane.  Issued through inline asm so that the compiler's
+// conservative LDS-DMA tracking (which cannot tell our ring buffers apart
+// once the read pointer is opaque) does not insert vmcnt(0) before every LDS
+// read; all waits for these transfers are explicit (pipeline_wait).  The
+// instruction writes no register; M0 is set inside the block, with the one
+// wait state the M0 -> LDS-DMA dependency needs.
+typedef int v4i __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4i dma_rsrc(const double* base, int32_t nbytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  v4i r;
+  r.x = int(uint32_t(a));
+  r.y = int(uint32_t(a >> 32) & 0xffffu);  // stride 0
+  r.z = nbytes;
+  r.w = kRsrcWord3;
+  return r;
+}
+__device__ __forceinline__ void dma16(v4i r, uint32_t voff, uint32_t lds) {
+  asm volatile(
+      "s_mov_b32 m0, %2\n\t"
+      "s_nop 0\n\t"
+      "buffer_load_dwordx4 %0, %1, 0 offen lds"
+      :
+      : "v"(voff), "s"(r), "s"(lds)
+      : "memory", "m0");
+}
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return uint32_t(reinterpret_cast<uintptr_t>(
+      (const __attribute__((address_space(3))) char*)(p)));
+}
+__device__ __forceinline__ v4i slot_dma_rsrc(const double* u, int64_t sf,
+                                             int s, int32_t nbytes) {
+  const double* b = u;
+  asm volatile("" : "+s"(b));
+  return dma_rsrc(b + s * sf, nbytes);
+}
+
 template <class Geo>
 __device__ __forceinline__ void dma_issue(const Patch& P, int slot,
                                           double* buf, int wave,
                                           const uint32_t (&off)[Geo::L]) {
-  const auto r = slot_rsrc(P.u_s, P.sf, slot, int32_t(P.sf * 8));
+  const v4i r = slot_dma_rsrc(P.u_s, P.sf, slot, int32_t(P.sf * 8));
+  const uint32_t l0 = lds_addr(buf) + uint32_t(wave * Geo::L) * 1024u;
 #pragma unroll
-  for (int j = 0; j < Geo::L; ++j) {
-    lds_ptr_t dst = (lds_ptr_t)(buf + (wave * Geo::L + j) * 128);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, dst, 16, int(off[j]), 0, 0,
-                                             0);
+  for (int j = 0; j < Geo::L; ++j) dma16(r, off[j], l0 + j * 1024u);
+}
+
+// Centre values the algebra needs before (or after) the slot's own phase:
+// gt_ij and beta^i at phase 0, A~_ij, phi, K, alpha at the alpha phase.  For
+// order 4 they come from a per-tile LDS block (18 slots x 256 points) that
+// is fetched by DMA one tile ahead, at phase kCentrePhase of the previous
+// tile; ordinary global loads would make the in-order vmcnt wait for every
+// prefetch issued before them.
+constexpr int kNCentre = 18;
+constexpr int kCentreSlots[kNCentre] = {GXX, GXY, GXZ, GYY, GYZ, GZZ,
+                                        BETX, BETY, BETZ, AXX, AXY, AXZ,
+                                        AYY, AYZ, AZZ, PHI, TRK, ALP};
+__host__ __device__ constexpr int centre_index(int slot) {
+  return slot <= GZZ && slot >= GXX   ? slot - GXX
+         : slot >= BETX && slot <= BETZ ? 6 + slot - BETX
+         : slot >= AXX && slot <= AZZ   ? 9 + slot - AXX
+         : slot == PHI                  ? 15
+         : slot == TRK                  ? 16
+                                        : 17;
+}
+constexpr int kCentrePhase = 11;  // alpha (phase 10) was the last reader
+constexpr int kCentreL = kNCentre * 128 / 256;  // DMA instructions per wave
+
+// Per-lane DMA offsets of the centre block of the tile at (x0, y0, z0):
+// instruction j of wave w moves half of slot kCentreSlots[(9w + j) / 2].
+__device__ __forceinline__ void centre_dma(const Patch& P, double* sc,
+                                           int x0, int y0, int z0, int wave,
+                                           int lane) {
+  const int g = P.ghost;
+#pragma unroll
+  for (int j = 0; j < kCentreL; ++j) {
+    const int ins = wave * kCentreL + j;
+    const int slot = kCentreSlots[ins >> 1];
+    const int within = (ins & 1) * 64 + lane;
+    const int row = within >> 3, col = within & 7;
+    const int tz = row >> 2, ty = row & 3;
+    const int64_t e = int64_t(z0 + tz + g) * P.sz + int64_t(y0 + ty + g) * P.sy +
+                      (x0 + g) + 2 * col;
+    dma16(slot_dma_rsrc(P.u_s, P.sf, slot, int32_t(P.sf * 8)),
+          uint32_t(e * 8), lds_addr(sc) + uint32_t(ins) * 1024u);
   }
 }
 
 // Loader used by point_rhs inside the pipelined kernel.
-template <class Geo>
+template <class Geo, bool CLDS>
 struct LdLds {
   const Patch* P;
   double* const* buf;      // NBUF buffers
+  double* sc;              // centre block (CLDS)
   const uint32_t* off_cur;  // this tile's DMA offsets
   const uint32_t* off_nxt;  // next tile's
-  int wave;
+  int nxt[3];              // next tile's origin (centre block prefetch)
+  int wave, lane, tid;
   int cidx;                // element index of the thread's centre in a box
   uint32_t vc;             // byte offset of the thread's point in a slot
   int32_t nbytes;
-  mutable const double* cur;
+  // this thread's centre in the current phase's buffer; set per phase
+  // through an opaque move so the compiler derives every tap from this one
+  // register with immediate offsets instead of hoisting (and spilling) a
+  // base address per buffer out of the tile loop
+  mutable const lds_double* pc;
 
   __device__ __forceinline__ double g(int s) const {
-    return bload(slot_rsrc(P->u_s, P->sf, s, nbytes), vc, 0);
+    if constexpr (CLDS)
+      return ((const lds_double*)sc)[centre_index(s) * 256 + tid];
+    else
+      return bload(slot_rsrc(P->u_s, P->sf, s, nbytes), vc, 0);
   }
   __device__ __forceinline__ void enter(int s) const {
     const int p = phase_of(s);
-    phase(p);
-    cur = buf[p % Geo::NBUF];
+    if (p != 0) phase(p);  // the kernel runs phase 0 itself
+    const lds_double* b = (const lds_double*)(buf[p % Geo::NBUF]) + cidx;
+    asm volatile("" : "+v"(b));
+    pc = b;
   }
   // one pipeline step at phase p (0 <= p < NPH)
   __device__ __forceinline__ void phase(int p) const {
-    // at most (NBUF-2)*L newer DMA instructions than phase p's may be in
-    // flight: then phase p's box has landed for this wave
-    asm volatile("s_waitcnt vmcnt(%0)" ::"n"((Geo::NBUF - 2) * Geo::L)
-                 : "memory");
+    // Wait until this wave's DMA for phase p has landed: newer than it are
+    // the prefetches of phases p+1 .. p+NBUF-2 and, for the NBUF-1 phases
+    // after kCentrePhase, the centre block.
+    // lgkmcnt(0): this wave's reads of the buffer about to be refilled
+    // have completed before it reaches the barrier.
+    if (CLDS && p > kCentrePhase && p < kCentrePhase + Geo::NBUF)
+      asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(
+                       (Geo::NBUF - 2) * Geo::L + kCentreL)
+                   : "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(
+                       (Geo::NBUF - 2) * Geo::L)
+                   : "memory");
     __builtin_amdgcn_s_barrier();
     const int q = p + Geo::NBUF - 1;  // phase to prefetch
     double* dst = buf[q % Geo::NBUF];
+    uint32_t o[Geo::L];
     if (q < Geo::NPH) {
-      if (q < NSLOT) {
-        uint32_t o[Geo::L];
 #pragma unroll
-        for (int j = 0; j < Geo::L; ++j) o[j] = off_cur[j];
-        dma_issue<Geo>(*P, kPhaseSlot[q], dst, wave, o);
-      } else {
-        uint32_t o[Geo::L];
-#pragma unroll
-        for (int j = 0; j < Geo::L; ++j) o[j] = off_cur[j];
-        dma_issue<Geo>(*P, kPhaseSlot[0], dst, wave, o);  // idle phase
-      }
+      for (int j = 0; j < Geo::L; ++j) o[j] = off_cur[j];
+      // idle phases (order 8) reload slot 0 to keep the counts uniform
+      dma_issue<Geo>(*P, q < NSLOT ? kPhaseSlot[q] : kPhaseSlot[0], dst, wave,
+                     o);
     } else {
       const int qn = q - Geo::NPH;
-      uint32_t o[Geo::L];
 #pragma unroll
       for (int j = 0; j < Geo::L; ++j) o[j] = off_nxt[j];
       dma_issue<Geo>(*P, qn < NSLOT ? kPhaseSlot[qn] : kPhaseSlot[0], dst,
                      wave, o);
     }
+    if (CLDS && p == kCentrePhase)
+      centre_dma(*P, sc, nxt[0], nxt[1], nxt[2], wave, lane);
   }
   __device__ __forceinline__ int str(int a) const {
     return a == 0 ? 1 : (a == 1 ? Geo::W : Geo::W * Geo::H);
   }
-  __device__ __forceinline__ double c(int) const { return cur[cidx]; }
+  __device__ __forceinline__ double c(int) const { return pc[0]; }
   __device__ __forceinline__ double ax(int, int a, int k) const {
-    return cur[cidx + k * str(a)];
+    return pc[k * str(a)];
   }
   __device__ __forceinline__ double pl(int, int a, int i, int b, int j) const {
-    return cur[cidx + i * str(a) + j * str(b)];
+    return pc[i * str(a) + j * str(b)];
   }
 };
 
@@ -204,6 +297,8 @@ __global__ void __launch_bounds__(256)
   __shared__ __attribute__((aligned(16))) double s3[Geo::NBUF > 3 ? Geo::BUFD : 2];
   __shared__ __attribute__((aligned(16))) double s4[Geo::NBUF > 4 ? Geo::BUFD : 2];
   double* bufs[5] = {s0, s1, s2, s3, s4};
+  constexpr bool CLDS = (ORDER == 4);
+  __shared__ __attribute__((aligned(16))) double sc[CLDS ? kNCentre * 256 : 2];
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -221,42 +316,47 @@ __global__ void __launch_bounds__(256)
     z0 = iz * Geo::TZ;
   };
   uint32_t offA[Geo::L], offB[Geo::L];
-  int x0, y0, z0;
+  int x0, y0, z0, xn, yn, zn;
   {
     const int t0 = tile_of(lin, nwg, 0);
     origin(t0, x0, y0, z0);
     dma_offsets<Geo>(P, x0, y0, z0, wave, lane, offA);
-    int xn, yn, zn;
     const int t1 = ntile_mine > 1 ? tile_of(lin, nwg, 1) : t0;
     origin(t1, xn, yn, zn);
     dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
   }
-  // prologue: phases 0 .. NBUF-2 of the first tile
+  // prologue: centre block and phases 0 .. NBUF-2 of the first tile
+  if constexpr (CLDS) centre_dma(P, sc, x0, y0, z0, wave, lane);
 #pragma unroll
   for (int q = 0; q < Geo::NBUF - 1; ++q)
     dma_issue<Geo>(P, kPhaseSlot[q], bufs[q], wave, offA);
 
-  const double ihd[3] = {1.0 / P.h[0], 1.0 / P.h[1], 1.0 / P.h[2]};
   const int32_t nbytes = int32_t(P.sf * 8);
   const uint32_t sy8 = uint32_t(P.sy) * 8u, sz8 = uint32_t(P.sz) * 8u;
   for (int k = 0; k < ntile_mine; ++k) {
-    const int t = tile_of(lin, nwg, k);
-    origin(t, x0, y0, z0);
+    origin(tile_of(lin, nwg, k), x0, y0, z0);
     const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
     const bool active = x < P.n[0] && y < P.n[1] && z < P.n[2];
     const int g = P.ghost;
-    LdLds<Geo> ld;
+    LdLds<Geo, CLDS> ld;
     ld.P = &P;
     ld.buf = bufs;
+    ld.sc = sc;
     ld.off_cur = offA;
     ld.off_nxt = offB;
+    ld.nxt[0] = xn;
+    ld.nxt[1] = yn;
+    ld.nxt[2] = zn;
     ld.wave = wave;
+    ld.lane = lane;
+    ld.tid = tid;
     ld.cidx = ((tz + Geo::R) * Geo::H + (ty + Geo::R)) * Geo::W + tx +
               Geo::R + 1;
     ld.vc = active ? uint32_t(z + g) * sz8 + uint32_t(y + g) * sy8 +
                          uint32_t(x + g) * 8u
                    : 0u;
     ld.nbytes = nbytes;
+    ld.phase(0);  // phase 0's box and this tile's centre block have landed
     const double xc = P.origin[0] + x * P.h[0];
     const double yc = P.origin[1] + y * P.h[1];
     const double zc = P.origin[2] + z * P.h[2];
@@ -275,13 +375,13 @@ __global__ void __launch_bounds__(256)
     }
     if (f64) {
       double r[NSLOT];
-      point_rhs<ORDER, double>(ld, ihd, xc, yc, zc, G, r);
+      point_rhs<ORDER, double>(ld, P, xc, yc, zc, G, r);
 #pragma unroll
       for (int p = NSLOT; p < Geo::NPH; ++p) ld.phase(p);  // idle phases
       if (active) epilogue<double>(P, stage, r, ld.vc, nbytes);
     } else {
       float r[NSLOT];
-      point_rhs<ORDER, float>(ld, ihd, xc, yc, zc, G, r);
+      point_rhs<ORDER, float>(ld, P, xc, yc, zc, G, r);
 #pragma unroll
       for (int p = NSLOT; p < Geo::NPH; ++p) ld.phase(p);
       if (active) epilogue<float>(P, stage, r, ld.vc, nbytes);
@@ -290,7 +390,6 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int j = 0; j < Geo::L; ++j) offA[j] = offB[j];
     if (k + 2 < ntile_mine) {
-      int xn, yn, zn;
       origin(tile_of(lin, nwg, k + 2), xn, yn, zn);
       dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
     }

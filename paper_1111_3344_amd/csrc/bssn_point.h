@@ -229,8 +229,9 @@ __device__ __forceinline__ float t_exp<float>(float x) {
 // enter(s) starts the phase of slot s (slots are entered in the order of
 // kPhaseSlot); c(s), ax(s, a, k), pl(s, a, i, b, j) read slot s inside its
 // phase (centre, offset k along axis a, offsets i along a and j along b).
-template <int ORDER, typename T, class L>
-__device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
+// Sp: inverse spacings ih[3], ih2[3], ihm[3] (xy, xz, yz), uniform.
+template <int ORDER, typename T, class L, class Sp>
+__device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
                                           double xc, double yc, double zc,
                                           const Gauge& G, T (&r)[NSLOT]) {
   using F = FD<ORDER>;
@@ -238,11 +239,10 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
   T ih[3], ih2[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    ih[a] = T(ihd[a]);
-    ih2[a] = T(ihd[a] * ihd[a]);
+    ih[a] = T(sp.ih[a]);
+    ih2[a] = T(sp.ih2[a]);
   }
-  const T ihxy = T(ihd[0] * ihd[1]), ihxz = T(ihd[0] * ihd[2]),
-          ihyz = T(ihd[1] * ihd[2]);
+  const T ihxy = T(sp.ihm[0]), ihxz = T(sp.ihm[1]), ihyz = T(sp.ihm[2]);
 
   // centre values used by the algebra
   const T phi = T(ld.g(PHI)), trK = T(ld.g(TRK)), alpha = T(ld.g(ALP));
@@ -276,7 +276,7 @@ __device__ __forceinline__ void point_rhs(const L& ld, const double (&ihd)[3],
     for (int k = -R; k <= R; ++k) {
       if (k == 0) continue;
       const double W = pos ? F::up(k) : -F::up(-k);
-      cw[a][WI<R>(k)] = T((bb * W + G.ko_eps * F::ko(k)) * ihd[a]);
+      cw[a][WI<R>(k)] = T((bb * W + G.ko_eps * F::ko(k)) * sp.ih[a]);
     }
   }
 

@@ -119,34 +119,51 @@ __device__ __forceinline__ bool tile_needs_fp64(const Patch& P, bool active,
   return m < thr;
 }
 
-// Stage epilogue: k -> acc / out (FP64).
+// Stage epilogue: k -> acc / out (FP64).  Every load is issued before the
+// first store (the compiler cannot prove the stores of one slot miss the
+// loads of the next, so interleaving them would serialise 25 round trips).
 template <typename T>
 __device__ __forceinline__ void epilogue(const Patch& P, int stage,
                                          const T (&r)[NSLOT], uint32_t vc,
                                          int32_t nbytes) {
   const double dt = P.dt;
+  if (stage == ST_RHS) {
 #pragma unroll
-  for (int s = 0; s < NSLOT; ++s) {
-    const double k = double(r[s]);
-    auto ro = rsrc(P.out + s * P.sf, nbytes);
-    if (stage == ST_RHS) {
-      bstore(ro, vc, k);
-      continue;
+    for (int s = 0; s < NSLOT; ++s)
+      bstore(rsrc(P.out + s * P.sf, nbytes), vc, double(r[s]));
+    return;
+  }
+  double un[NSLOT], ac[NSLOT];
+  if (stage != ST_3) {
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s)
+      un[s] = bload(rsrc(P.u_n + s * P.sf, nbytes), vc, 0);
+  }
+  if (stage != ST_0) {
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s)
+      ac[s] = bload(rsrc(P.acc + s * P.sf, nbytes), vc, 0);
+  }
+  BSSN_PHASE();  // loads above, stores below
+  if (stage == ST_3) {
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s)
+      bstore(rsrc(P.out + s * P.sf, nbytes), vc,
+             ac[s] + (dt / 6.0) * double(r[s]));
+  } else if (stage == ST_0) {
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      const double k = double(r[s]);
+      bstore(rsrc(P.acc + s * P.sf, nbytes), vc, un[s] + (dt / 6.0) * k);
+      bstore(rsrc(P.out + s * P.sf, nbytes), vc, un[s] + (dt / 2.0) * k);
     }
-    auto ra = rsrc(P.acc + s * P.sf, nbytes);
-    if (stage == ST_3) {
-      const double a = bload(ra, vc, 0);
-      bstore(ro, vc, a + (dt / 6.0) * k);
-    } else {
-      const double un = bload(rsrc(P.u_n + s * P.sf, nbytes), vc, 0);
-      if (stage == ST_0) {
-        bstore(ra, vc, un + (dt / 6.0) * k);
-        bstore(ro, vc, un + (dt / 2.0) * k);
-      } else {
-        const double a = bload(ra, vc, 0);
-        bstore(ra, vc, a + (dt / 3.0) * k);
-        bstore(ro, vc, un + (stage == ST_1 ? dt / 2.0 : dt) * k);
-      }
+  } else {
+    const double c = stage == ST_1 ? dt / 2.0 : dt;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      const double k = double(r[s]);
+      bstore(rsrc(P.acc + s * P.sf, nbytes), vc, ac[s] + (dt / 3.0) * k);
+      bstore(rsrc(P.out + s * P.sf, nbytes), vc, un[s] + c * k);
     }
   }
 }
@@ -161,7 +178,6 @@ __device__ __forceinline__ void stage_point(const Patch& P, const Gauge& G,
   const uint32_t sy8 = uint32_t(P.sy) * 8u, sz8 = uint32_t(P.sz) * 8u;
   const uint32_t vc =
       uint32_t(z + g) * sz8 + uint32_t(y + g) * sy8 + uint32_t(x + g) * 8u;
-  const double ihd[3] = {1.0 / P.h[0], 1.0 / P.h[1], 1.0 / P.h[2]};
   const double xc = P.origin[0] + x * P.h[0];
   const double yc = P.origin[1] + y * P.h[1];
   const double zc = P.origin[2] + z * P.h[2];
@@ -175,7 +191,7 @@ __device__ __forceinline__ void stage_point(const Patch& P, const Gauge& G,
     ld.str[0] = 8u;
     ld.str[1] = sy8;
     ld.str[2] = sz8;
-    point_rhs<ORDER, T>(ld, ihd, xc, yc, zc, G, r);
+    point_rhs<ORDER, T>(ld, P, xc, yc, zc, G, r);
   } else {
     LdPeriodic<R> ld;
     ld.u = P.u_s;
@@ -191,7 +207,7 @@ __device__ __forceinline__ void stage_point(const Patch& P, const Gauge& G,
         q = q < 0 ? q + P.n[a] : (q >= P.n[a] ? q - P.n[a] : q);
         ld.o[a][R + k] = uint32_t(q + g) * st[a];
       }
-    point_rhs<ORDER, T>(ld, ihd, xc, yc, zc, G, r);
+    point_rhs<ORDER, T>(ld, P, xc, yc, zc, G, r);
   }
   epilogue<T>(P, stage, r, vc, nbytes);
 }
