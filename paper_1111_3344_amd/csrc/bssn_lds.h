@@ -37,10 +37,10 @@ struct TileGeo<4> {
   static constexpr int R = 3, TX = 16, TY = 4, TZ = 4;
   static constexpr int W = 24;  // (TX + 2R + 1) rounded up to even
   static constexpr int H = TY + 2 * R, D = TZ + 2 * R;
-  static constexpr int G = W * H * D / 2;         // granules per box
-  static constexpr int L = (G + 255) / 256;       // DMA instructions per wave
-  static constexpr int NBUF = 5, NPH = 25;        // NPH % NBUF == 0
-  static constexpr int BUFD = L * 256 * 2;        // doubles per buffer
+  static constexpr int G = W * H * D / 2;    // granules per box
+  static constexpr int L = (G + 255) / 256;  // DMA instructions per wave
+  static constexpr int NBUF = 6;             // ring of boxes in LDS
+  static constexpr int BUFD = L * 256 * 2;   // doubles per buffer
 };
 template <>
 struct TileGeo<8> {
@@ -49,7 +49,7 @@ struct TileGeo<8> {
   static constexpr int H = TY + 2 * R, D = TZ + 2 * R;
   static constexpr int G = W * H * D / 2;
   static constexpr int L = (G + 255) / 256;
-  static constexpr int NBUF = 3, NPH = 27;  // two idle phases per tile
+  static constexpr int NBUF = 3;
   static constexpr int BUFD = L * 256 * 2;
 };
 
@@ -142,25 +142,21 @@ __device__ __forceinline__ void dma_issue(const Patch& P, int slot,
   for (int j = 0; j < Geo::L; ++j) dma16(r, off[j], l0 + j * 1024u);
 }
 
-// Centre values the algebra needs before (or after) the slot's own phase:
-// gt_ij and beta^i at phase 0, A~_ij, phi, K, alpha at the alpha phase.  For
-// order 4 they come from a per-tile LDS block (18 slots x 256 points) that
-// is fetched by DMA one tile ahead, at phase kCentrePhase of the previous
-// tile; ordinary global loads would make the in-order vmcnt wait for every
-// prefetch issued before them.
-constexpr int kNCentre = 18;
-constexpr int kCentreSlots[kNCentre] = {GXX, GXY, GXZ, GYY, GYZ, GZZ,
-                                        BETX, BETY, BETZ, AXX, AXY, AXZ,
-                                        AYY, AYZ, AZZ, PHI, TRK, ALP};
+// Centre values the algebra needs before the slot's own phase (gt_ij,
+// beta^i, alpha at phase 0) come from a per-tile LDS block (10 slots x 256
+// points) that is fetched by DMA one tile ahead, at phase kCentrePhase of
+// the previous tile, right after phase 0 read it; ordinary global loads
+// would make the in-order vmcnt wait for every prefetch issued before them.
+// Other centre values are taken from the slot's own box in its phase.
+constexpr int kNCentre = 10;
+constexpr int kCentreSlots[kNCentre] = {GXX,  GXY,  GXZ,  GYY, GYZ,
+                                        GZZ,  BETX, BETY, BETZ, ALP};
 __host__ __device__ constexpr int centre_index(int slot) {
-  return slot <= GZZ && slot >= GXX   ? slot - GXX
+  return slot <= GZZ && slot >= GXX     ? slot - GXX
          : slot >= BETX && slot <= BETZ ? 6 + slot - BETX
-         : slot >= AXX && slot <= AZZ   ? 9 + slot - AXX
-         : slot == PHI                  ? 15
-         : slot == TRK                  ? 16
-                                        : 17;
+                                        : 9;
 }
-constexpr int kCentrePhase = 11;  // alpha (phase 10) was the last reader
+constexpr int kCentrePhase = 1;
 constexpr int kCentreL = kNCentre * 128 / 256;  // DMA instructions per wave
 
 // Per-lane DMA offsets of the centre block of the tile at (x0, y0, z0):
@@ -183,46 +179,46 @@ __device__ __forceinline__ void centre_dma(const Patch& P, double* sc,
   }
 }
 
-// Loader used by point_rhs inside the pipelined kernel.
-template <class Geo, bool CLDS>
+// Loader used by point_rhs inside the pipelined kernel.  Phase p of the
+// k-th tile of a workgroup is global phase k*NSLOT + p and uses ring buffer
+// (k*NSLOT + p) mod NBUF.
+template <class Geo>
 struct LdLds {
   const Patch* P;
-  double* const* buf;      // NBUF buffers
-  double* sc;              // centre block (CLDS)
+  double* ring;            // NBUF buffers of BUFD doubles
+  double* sc;              // centre block
   const uint32_t* off_cur;  // this tile's DMA offsets
   const uint32_t* off_nxt;  // next tile's
   int nxt[3];              // next tile's origin (centre block prefetch)
+  int pbase;               // (k * NSLOT) mod NBUF
   int wave, lane, tid;
   int cidx;                // element index of the thread's centre in a box
-  uint32_t vc;             // byte offset of the thread's point in a slot
-  int32_t nbytes;
   // this thread's centre in the current phase's buffer; set per phase
   // through an opaque move so the compiler derives every tap from this one
   // register with immediate offsets instead of hoisting (and spilling) a
   // base address per buffer out of the tile loop
   mutable const lds_double* pc;
 
+  __device__ __forceinline__ double* buffer(int p) const {
+    return ring + ((pbase + p) % Geo::NBUF) * Geo::BUFD;
+  }
   __device__ __forceinline__ double g(int s) const {
-    if constexpr (CLDS)
-      return ((const lds_double*)sc)[centre_index(s) * 256 + tid];
-    else
-      return bload(slot_rsrc(P->u_s, P->sf, s, nbytes), vc, 0);
+    return ((const lds_double*)sc)[centre_index(s) * 256 + tid];
   }
   __device__ __forceinline__ void enter(int s) const {
     const int p = phase_of(s);
     if (p != 0) phase(p);  // the kernel runs phase 0 itself
-    const lds_double* b = (const lds_double*)(buf[p % Geo::NBUF]) + cidx;
+    const lds_double* b = (const lds_double*)buffer(p) + cidx;
     asm volatile("" : "+v"(b));
     pc = b;
   }
-  // one pipeline step at phase p (0 <= p < NPH)
+  // one pipeline step at phase p (0 <= p < NSLOT)
   __device__ __forceinline__ void phase(int p) const {
     // Wait until this wave's DMA for phase p has landed: newer than it are
-    // the prefetches of phases p+1 .. p+NBUF-2 and, for the NBUF-1 phases
-    // after kCentrePhase, the centre block.
-    // lgkmcnt(0): this wave's reads of the buffer about to be refilled
-    // have completed before it reaches the barrier.
-    if (CLDS && p > kCentrePhase && p < kCentrePhase + Geo::NBUF)
+    // the prefetches of phases p+1 .. p+NBUF-2 and, for phases 2 .. NBUF,
+    // the centre block issued at phase 1.  lgkmcnt(0): this wave's reads of
+    // the buffer about to be refilled have completed.
+    if (p > kCentrePhase && p <= kCentrePhase + Geo::NBUF - 1)
       asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(
                        (Geo::NBUF - 2) * Geo::L + kCentreL)
                    : "memory");
@@ -232,22 +228,17 @@ struct LdLds {
                    : "memory");
     __builtin_amdgcn_s_barrier();
     const int q = p + Geo::NBUF - 1;  // phase to prefetch
-    double* dst = buf[q % Geo::NBUF];
     uint32_t o[Geo::L];
-    if (q < Geo::NPH) {
+    if (q < NSLOT) {
 #pragma unroll
       for (int j = 0; j < Geo::L; ++j) o[j] = off_cur[j];
-      // idle phases (order 8) reload slot 0 to keep the counts uniform
-      dma_issue<Geo>(*P, q < NSLOT ? kPhaseSlot[q] : kPhaseSlot[0], dst, wave,
-                     o);
+      dma_issue<Geo>(*P, kPhaseSlot[q], buffer(q), wave, o);
     } else {
-      const int qn = q - Geo::NPH;
 #pragma unroll
       for (int j = 0; j < Geo::L; ++j) o[j] = off_nxt[j];
-      dma_issue<Geo>(*P, qn < NSLOT ? kPhaseSlot[qn] : kPhaseSlot[0], dst,
-                     wave, o);
+      dma_issue<Geo>(*P, kPhaseSlot[q - NSLOT], buffer(q), wave, o);
     }
-    if (CLDS && p == kCentrePhase)
+    if (p == kCentrePhase)
       centre_dma(*P, sc, nxt[0], nxt[1], nxt[2], wave, lane);
   }
   __device__ __forceinline__ int str(int a) const {
@@ -262,25 +253,24 @@ struct LdLds {
   }
 };
 
-// tile t (linear, x fastest) -> interior coordinates of its origin
+// Tile walk.  Tiles are numbered z fastest within an (x, y) column:
+// t = iz + ntz * (ix + ntx * iy).  Workgroup b owns the contiguous range of
+// tiles [lo, hi) of position walk_pos(b) in an even split, so it marches
+// along z through whole columns (consecutive boxes share 2R of their
+// TZ + 2R planes, which the caches then serve), and the workgroups of one
+// XCD (dispatched round-robin: b, b+8, ...) own neighbouring columns, whose
+// x/y halos meet in that XCD's L2.
 struct TileMap {
   int ntx, nty, ntz, ntiles;
 };
-
-// Position of workgroup wg in the tile walk (XCD-aware): workgroups are
-// dispatched to the 8 XCDs round-robin, so wg, wg+8, ... share an XCD; they
-// get consecutive positions, hence neighbouring tiles.
 __host__ __device__ __forceinline__ int walk_pos(int wg, int nwg) {
   return (nwg & 7) == 0 ? (wg & 7) * (nwg >> 3) + (wg >> 3) : wg;
 }
-// k-th tile of the workgroup at walk position lin
-__host__ __device__ __forceinline__ int tile_of(int lin, int nwg, int k) {
-  return k * nwg + lin;
-}
-// number of tiles the workgroup at walk position lin processes
-__host__ __device__ __forceinline__ int tiles_of(int lin, int nwg,
-                                                 int ntiles) {
-  return ntiles > lin ? (ntiles - 1 - lin) / nwg + 1 : 0;
+__host__ __device__ __forceinline__ void walk_range(int lin, int nwg,
+                                                    int ntiles, int& lo,
+                                                    int& hi) {
+  lo = int((int64_t(ntiles) * lin) / nwg);
+  hi = int((int64_t(ntiles) * (lin + 1)) / nwg);
 }
 
 // MIXED = false: FP64 everywhere.  MIXED = true: per tile, FP32 stencils and
@@ -291,71 +281,64 @@ __global__ void __launch_bounds__(256)
     k_stage_lds(const Patch P, const Gauge G, const int stage,
                 const TileMap M) {
   using Geo = TileGeo<ORDER>;
-  __shared__ __attribute__((aligned(16))) double s0[Geo::BUFD];
-  __shared__ __attribute__((aligned(16))) double s1[Geo::BUFD];
-  __shared__ __attribute__((aligned(16))) double s2[Geo::BUFD];
-  __shared__ __attribute__((aligned(16))) double s3[Geo::NBUF > 3 ? Geo::BUFD : 2];
-  __shared__ __attribute__((aligned(16))) double s4[Geo::NBUF > 4 ? Geo::BUFD : 2];
-  double* bufs[5] = {s0, s1, s2, s3, s4};
-  constexpr bool CLDS = (ORDER == 4);
-  __shared__ __attribute__((aligned(16))) double sc[CLDS ? kNCentre * 256 : 2];
+  __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
+  __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int tx = lane & 15, ty = lane >> 4, tz = wave;
   const int nwg = gridDim.x;
-  const int lin = walk_pos(blockIdx.x, nwg);
-  const int ntile_mine = tiles_of(lin, nwg, M.ntiles);
-  if (ntile_mine == 0) return;
+  int tlo, thi;
+  walk_range(walk_pos(blockIdx.x, nwg), nwg, M.ntiles, tlo, thi);
+  const int ntile_mine = thi - tlo;
+  if (ntile_mine <= 0) return;
 
   auto origin = [&](int t, int& x0, int& y0, int& z0) {
-    const int ix = t % M.ntx, iy = (t / M.ntx) % M.nty, iz = t / (M.ntx * M.nty);
-    x0 = ix * Geo::TX;
-    y0 = iy * Geo::TY;
+    const int iz = t % M.ntz, col = t / M.ntz;
+    x0 = (col % M.ntx) * Geo::TX;
+    y0 = (col / M.ntx) * Geo::TY;
     z0 = iz * Geo::TZ;
   };
   uint32_t offA[Geo::L], offB[Geo::L];
   int x0, y0, z0, xn, yn, zn;
   {
-    const int t0 = tile_of(lin, nwg, 0);
-    origin(t0, x0, y0, z0);
+    origin(tlo, x0, y0, z0);
     dma_offsets<Geo>(P, x0, y0, z0, wave, lane, offA);
-    const int t1 = ntile_mine > 1 ? tile_of(lin, nwg, 1) : t0;
-    origin(t1, xn, yn, zn);
+    origin(ntile_mine > 1 ? tlo + 1 : tlo, xn, yn, zn);
     dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
   }
   // prologue: centre block and phases 0 .. NBUF-2 of the first tile
-  if constexpr (CLDS) centre_dma(P, sc, x0, y0, z0, wave, lane);
+  centre_dma(P, sc, x0, y0, z0, wave, lane);
 #pragma unroll
   for (int q = 0; q < Geo::NBUF - 1; ++q)
-    dma_issue<Geo>(P, kPhaseSlot[q], bufs[q], wave, offA);
+    dma_issue<Geo>(P, kPhaseSlot[q], ring + q * Geo::BUFD, wave, offA);
 
   const int32_t nbytes = int32_t(P.sf * 8);
   const uint32_t sy8 = uint32_t(P.sy) * 8u, sz8 = uint32_t(P.sz) * 8u;
   for (int k = 0; k < ntile_mine; ++k) {
-    origin(tile_of(lin, nwg, k), x0, y0, z0);
+    origin(tlo + k, x0, y0, z0);
     const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
     const bool active = x < P.n[0] && y < P.n[1] && z < P.n[2];
     const int g = P.ghost;
-    LdLds<Geo, CLDS> ld;
+    LdLds<Geo> ld;
     ld.P = &P;
-    ld.buf = bufs;
+    ld.ring = ring;
     ld.sc = sc;
     ld.off_cur = offA;
     ld.off_nxt = offB;
     ld.nxt[0] = xn;
     ld.nxt[1] = yn;
     ld.nxt[2] = zn;
+    ld.pbase = (k * NSLOT) % Geo::NBUF;
     ld.wave = wave;
     ld.lane = lane;
     ld.tid = tid;
     ld.cidx = ((tz + Geo::R) * Geo::H + (ty + Geo::R)) * Geo::W + tx +
               Geo::R + 1;
-    ld.vc = active ? uint32_t(z + g) * sz8 + uint32_t(y + g) * sy8 +
-                         uint32_t(x + g) * 8u
-                   : 0u;
-    ld.nbytes = nbytes;
+    const uint32_t vc = active ? uint32_t(z + g) * sz8 + uint32_t(y + g) * sy8 +
+                                     uint32_t(x + g) * 8u
+                               : 0u;
     ld.phase(0);  // phase 0's box and this tile's centre block have landed
     const double xc = P.origin[0] + x * P.h[0];
     const double yc = P.origin[1] + y * P.h[1];
@@ -376,21 +359,17 @@ __global__ void __launch_bounds__(256)
     if (f64) {
       double r[NSLOT];
       point_rhs<ORDER, double>(ld, P, xc, yc, zc, G, r);
-#pragma unroll
-      for (int p = NSLOT; p < Geo::NPH; ++p) ld.phase(p);  // idle phases
-      if (active) epilogue<double>(P, stage, r, ld.vc, nbytes);
+      if (active) epilogue<double>(P, stage, r, vc, nbytes);
     } else {
       float r[NSLOT];
       point_rhs<ORDER, float>(ld, P, xc, yc, zc, G, r);
-#pragma unroll
-      for (int p = NSLOT; p < Geo::NPH; ++p) ld.phase(p);
-      if (active) epilogue<float>(P, stage, r, ld.vc, nbytes);
+      if (active) epilogue<float>(P, stage, r, vc, nbytes);
     }
     // next tile: its offsets become current, prepare the one after
 #pragma unroll
     for (int j = 0; j < Geo::L; ++j) offA[j] = offB[j];
     if (k + 2 < ntile_mine) {
-      origin(tile_of(lin, nwg, k + 2), xn, yn, zn);
+      origin(tlo + k + 2, xn, yn, zn);
       dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
     }
   }

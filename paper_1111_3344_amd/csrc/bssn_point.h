@@ -115,22 +115,24 @@ struct FD<8> {
   }
 };
 
-// Order in which point_rhs visits the slots (one phase per slot).
-constexpr int kPhaseSlot[NSLOT] = {GXX,  GXY,  GXZ,  GYY,  GYZ,  GZZ, GAMX,
-                                   GAMY, GAMZ, PHI,  ALP,  TRK,  BETX, BETY,
-                                   BETZ, AXX,  AXY,  AXZ,  AYY,  AYZ,  AZZ,
-                                   BX,   BY,   BZ,   ADOT};
-// inverse of kPhaseSlot (non-recursive, so it folds after unrolling)
+// Order in which point_rhs visits the slots (one phase per slot).  Slots
+// that only need advection and dissipation (A~, B, A) alternate with the
+// heavy ones, so that the time between a prefetch and its use stays even.
+constexpr int kPhaseSlot[NSLOT] = {GXX,  AXX,  GXY, AXY, GXZ,  AXZ,  GYY,
+                                   AYY,  GYZ,  AYZ, GZZ, AZZ,  GAMX, BX,
+                                   GAMY, BY,   GAMZ, BZ, PHI,  ADOT, TRK,
+                                   ALP,  BETX, BETY, BETZ};
+// inverse of kPhaseSlot (a formula, so it folds after unrolling)
 __host__ __device__ constexpr int phase_of(int slot) {
-  return slot == PHI   ? 9
-         : slot <= GZZ ? slot - GXX
-         : slot == TRK ? 11
-         : slot <= AZZ ? 15 + (slot - AXX)
-         : slot <= GAMZ ? 6 + (slot - GAMX)
-         : slot == ALP ? 10
-         : slot <= BETZ ? 12 + (slot - BETX)
-         : slot <= BZ   ? 21 + (slot - BX)
-                        : 24;
+  return slot >= GXX && slot <= GZZ   ? 2 * (slot - GXX)
+         : slot >= AXX && slot <= AZZ ? 2 * (slot - AXX) + 1
+         : slot >= GAMX && slot <= GAMZ ? 12 + 2 * (slot - GAMX)
+         : slot >= BX && slot <= BZ     ? 13 + 2 * (slot - BX)
+         : slot == PHI                  ? 18
+         : slot == ADOT                 ? 19
+         : slot == TRK                  ? 20
+         : slot == ALP                  ? 21
+                                        : 22 + (slot - BETX);
 }
 
 // symmetric pair -> 0..5 (xx xy xz yy yz zz)
@@ -244,14 +246,11 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
   }
   const T ihxy = T(sp.ihm[0]), ihxz = T(sp.ihm[1]), ihyz = T(sp.ihm[2]);
 
-  // centre values used by the algebra
-  const T phi = T(ld.g(PHI)), trK = T(ld.g(TRK)), alpha = T(ld.g(ALP));
-  T gt[6], At[6];
+  // centre values needed from the start: gt_ij, beta^i, alpha
+  T gt[6];
 #pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    gt[m] = T(ld.g(GXX + m));
-    At[m] = T(ld.g(AXX + m));
-  }
+  for (int m = 0; m < 6; ++m) gt[m] = T(ld.g(GXX + m));
+  const T alpha = T(ld.g(ALP));
 
   // inverse conformal metric (adjugate / determinant)
   const T c00 = gt[3] * gt[5] - gt[4] * gt[4];
@@ -280,9 +279,11 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
     }
   }
 
-  // ---- gt_ij: first derivatives, trace of second derivatives into R~ ----
+  // ---- gt_ij (first derivatives; trace of the second derivatives into
+  //      R~), alternating with A~_ij (advection only; centre value kept) --
   T dgt[6][3];
   T Rt[6];
+  T At[6];
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
     T d2[3];
@@ -296,6 +297,10 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
     Rt[m] = T(-0.5) * (gu[0] * d2[0] + gu[3] * d2[1] + gu[5] * d2[2] +
                        T(2) * (gu[1] * dxy + gu[2] * dxz + gu[4] * dyz));
     keep(Rt[m]);
+    ld.enter(AXX + m);
+    At[m] = T(ld.c(AXX + m));
+    r[AXX + m] = star<ORDER, T, false, false>(ld, AXX + m, cw, ih, ih2,
+                                              nullptr, nullptr);
   }
 
   // Christoffel symbols: Gl[i][S(j,k)] = Gamma~_ijk, Gu[i][S(j,k)] =
@@ -364,7 +369,8 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
       }
   }
 
-  // ---- Gt^k: d_j Gt^k into R~_ij ----
+  // ---- Gt^k (d_j Gt^k into R~_ij), alternating with B^k --------------------
+  T Bv[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     T dG[3];
@@ -376,13 +382,18 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
 #pragma unroll
       for (int j = i; j < 3; ++j)
         Rt[S(i, j)] += T(0.5) * (gt[S(k, i)] * dG[j] + gt[S(k, j)] * dG[i]);
+    ld.enter(BX + k);
+    Bv[k] = T(ld.c(BX + k));
+    r[BX + k] = star<ORDER, T, false, false>(ld, BX + k, cw, ih, ih2, nullptr,
+                                             nullptr);
   }
 
-  // ---- phi: R^phi_ij ----
+  // ---- phi: R^phi_ij into R~_ij ------------------------------------------------
   T dphi[3];
+  ld.enter(PHI);
+  const T phi = T(ld.c(PHI));
   {
     T d2[3];
-    ld.enter(PHI);
     r[PHI] = star<ORDER, T, true, true>(ld, PHI, cw, ih, ih2, dphi, d2);
     T dd[6];
     dd[0] = d2[0];
@@ -414,29 +425,28 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
       }
   }
 
-  // ---- alpha: X_ij, the A~ and K sources, part of Gt's source ----
-  const T em4phi = t_exp<T>(T(-4) * phi);
-  // A~^i_j, A~^ij and A~_ij A~^ij (only the alpha phase needs them)
-  T Aud[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      Aud[i][j] = gu[S(i, 0)] * At[S(0, j)] + gu[S(i, 1)] * At[S(1, j)] +
-                  gu[S(i, 2)] * At[S(2, j)];
-  T Auu[6];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = i; j < 3; ++j)
-      Auu[S(i, j)] = Aud[i][0] * gu[S(0, j)] + Aud[i][1] * gu[S(1, j)] +
-                     Aud[i][2] * gu[S(2, j)];
-  const T AA = At[0] * Auu[0] + At[3] * Auu[3] + At[5] * Auu[5] +
-               T(2) * (At[1] * Auu[1] + At[2] * Auu[2] + At[4] * Auu[4]);
+  // ---- A (advection only) ------------------------------------------------------
+  ld.enter(ADOT);
+  r[ADOT] = star<ORDER, T, false, false>(ld, ADOT, cw, ih, ih2, nullptr,
+                                         nullptr);
+
+  // ---- K: the -4/3 alpha gt^ij d_j K part of Gt's source ----------------------
   T Tg[3];
+  ld.enter(TRK);
+  const T trK = T(ld.c(TRK));
+  {
+    T dK[3];
+    r[TRK] = star<ORDER, T, true, false>(ld, TRK, cw, ih, ih2, dK, nullptr);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      Tg[i] = T(-4.0 / 3.0) * alpha *
+              (gu[S(i, 0)] * dK[0] + gu[S(i, 1)] * dK[1] + gu[S(i, 2)] * dK[2]);
+  }
+
+  // ---- alpha: X_ij, the A~ and K sources, the rest of Gt's source ---------
+  ld.enter(ALP);
   {
     T dalp[3], d2[3];
-    ld.enter(ALP);
     r[ALP] = star<ORDER, T, true, true>(ld, ALP, cw, ih, ih2, dalp, d2);
     T dd[6];
     dd[0] = d2[0];
@@ -446,6 +456,24 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
     dd[1] = mixed<ORDER, T>(ld, ALP, 0, 1, ihxy);
     dd[2] = mixed<ORDER, T>(ld, ALP, 0, 2, ihxz);
     dd[4] = mixed<ORDER, T>(ld, ALP, 1, 2, ihyz);
+    const T em4phi = t_exp<T>(T(-4) * phi);
+    // A~^i_j, A~^ij and A~_ij A~^ij
+    T Aud[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        Aud[i][j] = gu[S(i, 0)] * At[S(0, j)] + gu[S(i, 1)] * At[S(1, j)] +
+                    gu[S(i, 2)] * At[S(2, j)];
+    T Auu[6];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j)
+        Auu[S(i, j)] = Aud[i][0] * gu[S(0, j)] + Aud[i][1] * gu[S(1, j)] +
+                       Aud[i][2] * gu[S(2, j)];
+    const T AA = At[0] * Auu[0] + At[3] * Auu[3] + At[5] * Auu[5] +
+                 T(2) * (At[1] * Auu[1] + At[2] * Auu[2] + At[4] * Auu[4]);
     T DD[6], X[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m)
@@ -471,7 +499,7 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
         s -= T(2) * alpha *
              (At[S(i, 0)] * Aud[0][j] + At[S(i, 1)] * Aud[1][j] +
               At[S(i, 2)] * Aud[2][j]);
-        r[AXX + m] = s;  // advection of A~ is added below
+        r[AXX + m] += s;
       }
     const T trDD = gu[0] * DD[0] + gu[3] * DD[3] + gu[5] * DD[5] +
                    T(2) * (gu[1] * DD[1] + gu[2] * DD[2] + gu[4] * DD[4]);
@@ -481,8 +509,8 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
         gu[1] * (dphi[0] * dalp[1] + dphi[1] * dalp[0]) +
         gu[2] * (dphi[0] * dalp[2] + dphi[2] * dalp[0]) +
         gu[4] * (dphi[1] * dalp[2] + dphi[2] * dalp[1]);
-    r[TRK] = -em4phi * (trDD + T(2) * dpda) +
-             alpha * (AA + trK * trK * T(1.0 / 3.0));
+    r[TRK] += -em4phi * (trDD + T(2) * dpda) +
+              alpha * (AA + trK * trK * T(1.0 / 3.0));
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const T GA = Gu[i][0] * Auu[0] + Gu[i][3] * Auu[3] + Gu[i][5] * Auu[5] +
@@ -492,22 +520,11 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
                    Auu[S(i, 2)] * dalp[2];
       const T Ap = Auu[S(i, 0)] * dphi[0] + Auu[S(i, 1)] * dphi[1] +
                    Auu[S(i, 2)] * dphi[2];
-      Tg[i] = T(-2) * Ad + T(2) * alpha * (GA + T(6) * Ap);
+      Tg[i] += T(-2) * Ad + T(2) * alpha * (GA + T(6) * Ap);
     }
   }
 
-  // ---- K ----
-  {
-    T dK[3];
-    ld.enter(TRK);
-    r[TRK] += star<ORDER, T, true, false>(ld, TRK, cw, ih, ih2, dK, nullptr);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      Tg[i] -= T(4.0 / 3.0) * alpha *
-               (gu[S(i, 0)] * dK[0] + gu[S(i, 1)] * dK[1] + gu[S(i, 2)] * dK[2]);
-  }
-
-  // ---- beta^k: shift terms of gt, A~, Gt ----
+  // ---- beta^k: shift terms of gt, A~, Gt ------------------------------------
   T rg[6];
 #pragma unroll
   for (int m = 0; m < 6; ++m) rg[m] = T(0);
@@ -553,27 +570,7 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
   }
   r[PHI] += (divb - alpha * trK) * T(1.0 / 6.0);
 
-  // ---- advected-only parts: A~ (sources above), B, A ----
-#pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    ld.enter(AXX + m);
-    r[AXX + m] +=
-        star<ORDER, T, false, false>(ld, AXX + m, cw, ih, ih2, nullptr,
-                                     nullptr);
-  }
-  T Bv[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    ld.enter(BX + i);
-    Bv[i] = T(ld.c(BX + i));
-    r[BX + i] = star<ORDER, T, false, false>(ld, BX + i, cw, ih, ih2, nullptr,
-                                             nullptr);
-  }
-  ld.enter(ADOT);
-  r[ADOT] = star<ORDER, T, false, false>(ld, ADOT, cw, ih, ih2, nullptr,
-                                         nullptr);
-
-  // ---- gauge ----
+  // ---- gauge ---------------------------------------------------------------------
 #pragma unroll
   for (int i = 0; i < 3; ++i) r[GAMX + i] += Tg[i];
   if (!G.lapse_static) r[ALP] -= T(G.lapse_f) * alpha * trK;
