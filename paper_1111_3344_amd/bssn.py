@@ -137,9 +137,12 @@ def _stream(stream):
 
 
 def ptr(grid, t):
-    """Device address of the ghost corner of slot 0 of flat tensor t."""
+    """Device address of the ghost corner of slot 0 of flat tensor t (or of
+    a raw device address t that holds such a flat buffer)."""
     if t is None:
         return None
+    if isinstance(t, int):
+        return ctypes.c_void_p(t + 8 * grid.off0)
     if t.dtype.itemsize != 8:
         raise TypeError("state buffers are float64")
     return ctypes.c_void_p(t.data_ptr() + 8 * grid.off0)

@@ -1,0 +1,513 @@
+// bssn_batch.cpp -- many independent static patches advanced together (the
+// mesh-refinement picture of the paper's section on adaptive mesh
+// refinement: each refinement level is a set of independent component
+// grids of uneven sizes, all evolved with the same right-hand side).
+//
+// A plan sorts the patches into size classes (largest extent rounded up to
+// a multiple of 16 points), picks one kernel variant per class (timed trial
+// launches, or a default), and builds per variant a device work list over
+// all patches of the classes that chose it:
+//   VAR_LDS  runs of LDS tiles; the tiles of all its patches, in class and
+//            patch order, are split evenly over one persistent workgroup per
+//            compute unit, and each workgroup's share is cut at patch
+//            boundaries into items (patch, first tile, end tile);
+//   VAR_D*   one item per direct-kernel workgroup (patch, x0, y0, z).
+// The four stages of an RK4 step (one launch per variant in use per stage)
+// are captured once into a hipGraph; batch_patches replays it per step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/bssn.h"
+#include "bssn_api_internal.h"
+#include "bssn_internal.h"
+#include "bssn_kernels.h"
+
+namespace bssn {
+namespace {
+
+constexpr int kMaxPatches = 1 << 16;
+constexpr int kDirectBX[NVAR] = {0, 64, 32};
+constexpr int kTuneReps = 3;
+
+int class_extent(const bssn_grid& g) {
+  const int m = std::max(g.n[0], std::max(g.n[1], g.n[2]));
+  return (m + 15) / 16 * 16;
+}
+
+// Tile counts of patch g for the LDS kernel.
+void lds_tiles_of(const bssn_grid& g, int& ntx, int& nty, int& ntz) {
+  ntx = (g.n[0] + kLdsTile[0] - 1) / kLdsTile[0];
+  nty = (g.n[1] + kLdsTile[1] - 1) / kLdsTile[1];
+  ntz = (g.n[2] + kLdsTile[2] - 1) / kLdsTile[2];
+}
+
+// Host work list of one variant over a list of patches.
+struct HostGroup {
+  int variant = VAR_LDS;
+  int nwg = 0;                      // VAR_LDS workgroups
+  std::vector<LdsItem> lds;         // VAR_LDS items
+  std::vector<int32_t> wstart;      // VAR_LDS, nwg + 1
+  std::vector<DirectItem> direct;   // VAR_D*
+  size_t item_bytes() const {
+    return variant == VAR_LDS ? lds.size() * sizeof(LdsItem)
+                              : direct.size() * sizeof(DirectItem);
+  }
+  int nitems() const {
+    return int(variant == VAR_LDS ? lds.size() : direct.size());
+  }
+};
+
+int build_group(const std::vector<bssn_grid>& grids,
+                const std::vector<int>& pids, int variant, int nwg_max,
+                HostGroup& G) {
+  G = HostGroup();
+  G.variant = variant;
+  if (variant == VAR_LDS) {
+    std::vector<int64_t> start(pids.size() + 1, 0);
+    for (size_t i = 0; i < pids.size(); ++i) {
+      int ntx, nty, ntz;
+      lds_tiles_of(grids[pids[i]], ntx, nty, ntz);
+      start[i + 1] = start[i] + int64_t(ntx) * nty * ntz;
+    }
+    const int64_t T = start.back();
+    if (T >= (int64_t(1) << 31) / 2)
+      return fail(BSSN_EUNSUPPORTED, "batch: %lld LDS tiles exceed the "
+                  "work-list range", (long long)T);
+    const int nwg = int(std::min<int64_t>(nwg_max, T));
+    G.nwg = nwg;
+    G.wstart.assign(nwg + 1, 0);
+    size_t i = 0;  // patch whose tiles contain the current global tile
+    for (int q = 0; q < nwg; ++q) {
+      G.wstart[q] = int32_t(G.lds.size());
+      int64_t lo = T * q / nwg;
+      const int64_t hi = T * (q + 1) / nwg;
+      while (lo < hi) {
+        while (start[i + 1] <= lo) ++i;
+        const int64_t end = std::min(hi, start[i + 1]);
+        const bssn_grid& g = grids[pids[i]];
+        LdsItem it;
+        it.patch = pids[i];
+        it.tlo = int32_t(lo - start[i]);
+        it.thi = int32_t(end - start[i]);
+        lds_tiles_of(g, it.ntx, it.nty, it.ntz);
+        G.lds.push_back(it);
+        lo = end;
+      }
+    }
+    G.wstart[nwg] = int32_t(G.lds.size());
+    return BSSN_OK;
+  }
+  const int bx = kDirectBX[variant], by = 256 / bx;
+  int64_t count = 0;
+  for (int p : pids) {
+    const bssn_grid& g = grids[p];
+    count += int64_t((g.n[0] + bx - 1) / bx) * ((g.n[1] + by - 1) / by) *
+             g.n[2];
+  }
+  if (count >= (int64_t(1) << 31) - 1)
+    return fail(BSSN_EUNSUPPORTED, "batch: %lld workgroups exceed one launch",
+                (long long)count);
+  G.direct.reserve(size_t(count));
+  for (int p : pids) {
+    const bssn_grid& g = grids[p];
+    for (int z = 0; z < g.n[2]; ++z)
+      for (int y0 = 0; y0 < g.n[1]; y0 += by)
+        for (int x0 = 0; x0 < g.n[0]; x0 += bx)
+          G.direct.push_back(DirectItem{p, x0, y0, z});
+  }
+  return BSSN_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// Device copy of a group's work list (items, then wstart) at dst.
+size_t group_bytes(const HostGroup& G) {
+  return align256(G.item_bytes()) + align256(G.wstart.size() * 4);
+}
+hipError_t upload_group(const HostGroup& G, char* dst, BatchLaunch& L) {
+  L.variant = G.variant;
+  L.items = dst;
+  L.nitems = G.nitems();
+  L.nwg = G.nwg;
+  L.wstart = nullptr;
+  const void* src = G.variant == VAR_LDS ? (const void*)G.lds.data()
+                                         : (const void*)G.direct.data();
+  hipError_t e = hipMemcpy(dst, src, G.item_bytes(), hipMemcpyHostToDevice);
+  if (e != hipSuccess || G.variant != VAR_LDS) return e;
+  char* w = dst + align256(G.item_bytes());
+  L.wstart = reinterpret_cast<const int32_t*>(w);
+  return hipMemcpy(w, G.wstart.data(), G.wstart.size() * 4,
+                   hipMemcpyHostToDevice);
+}
+
+struct AddrRange {
+  hipDeviceptr_t base;
+  size_t size;
+};
+
+}  // namespace
+}  // namespace bssn
+
+using namespace bssn;
+
+struct bssn_batch_plan {
+  int device = -1;
+  int order = 4, precision = 0, np = 0;
+  Gauge G{};
+  std::vector<bssn_grid> grids;
+  std::vector<Patch> hp[4];           // per stage, per patch
+  std::vector<const void*> ptrs;      // every buffer the plan touches
+  std::vector<AddrRange> ranges;      // their allocations at plan time
+  struct Cls {
+    int extent, variant;
+    float ms[NVAR];
+    std::vector<int> pids;
+  };
+  std::vector<Cls> classes;
+  std::vector<int> var_of_patch;
+  char* dmem = nullptr;               // Patch[4][np], then work lists
+  std::vector<BatchLaunch> launches;  // one per variant in use (stage-free)
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  ~bssn_batch_plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (dmem) (void)hipFree(dmem);
+  }
+  const Patch* dpatches(int stage) const {
+    return reinterpret_cast<const Patch*>(dmem) + size_t(stage) * np;
+  }
+};
+
+namespace bssn {
+namespace {
+
+// Records the allocation of every buffer; returns BSSN_ESTALE when one of
+// them is no longer the allocation it was at plan time.
+int check_fresh(const bssn_batch_plan* plan) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != plan->device)
+    return fail(BSSN_ESTALE, "batch plan belongs to device %d, current is %d",
+                plan->device, dev);
+  for (size_t i = 0; i < plan->ptrs.size(); ++i) {
+    AddrRange r{};
+    e = hipMemGetAddressRange(&r.base, &r.size,
+                              (hipDeviceptr_t)plan->ptrs[i]);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();  // do not leave the query's error behind
+      return fail(BSSN_ESTALE, "batch plan buffer %zu (patch %zu) is no "
+                  "longer allocated", i % 4, i / 4);
+    }
+    if (r.base != plan->ranges[i].base || r.size != plan->ranges[i].size)
+      return fail(BSSN_ESTALE, "batch plan buffer %zu (patch %zu) lies in a "
+                  "different allocation than at plan time", i % 4, i / 4);
+  }
+  return BSSN_OK;
+}
+
+int record_graph(bssn_batch_plan* P) {
+  hipError_t e = hipStreamCreateWithFlags(&P->cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+  e = hipStreamBeginCapture(P->cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  hipError_t le = hipSuccess;
+  for (int s = 0; s < 4 && le == hipSuccess; ++s)
+    for (BatchLaunch L : P->launches) {
+      L.patches = P->dpatches(s);
+      le = launch_batch(L, P->G, P->order, s, P->precision, P->cs);
+      if (le != hipSuccess) break;
+    }
+  e = hipStreamEndCapture(P->cs, &P->graph);
+  if (le != hipSuccess) return hip_fail(le, "batch stage capture");
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return BSSN_OK;
+}
+
+// Milliseconds of one batched stage-0 launch of variant v over pids (best
+// of kTuneReps after one warm-up), or < 0 on failure.
+float time_variant(bssn_batch_plan* P, const std::vector<int>& pids, int v,
+                   hipStream_t st, int* rc) {
+  HostGroup H;
+  if ((*rc = build_group(P->grids, pids, v, persistent_groups(), H)))
+    return -1.f;
+  char* d = nullptr;
+  hipError_t e = hipMalloc((void**)&d, group_bytes(H));
+  if (e != hipSuccess) {
+    *rc = fail(BSSN_ENOMEM, "autotune work list: %s", hipGetErrorString(e));
+    return -1.f;
+  }
+  BatchLaunch L{};
+  e = upload_group(H, d, L);
+  L.patches = P->dpatches(0);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best = -1.f;
+  for (int r = 0; r <= kTuneReps && e == hipSuccess; ++r) {
+    e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch_batch(L, P->G, P->order, 0, P->precision, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && r > 0 && (best < 0.f || ms < best)) best = ms;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(d);
+  if (e != hipSuccess) {
+    *rc = hip_fail(e, "autotune launch");
+    return -1.f;
+  }
+  *rc = BSSN_OK;
+  return best;
+}
+
+int plan_build(bssn_batch_plan* P, int autotune, hipStream_t st) {
+  const int np = P->np;
+  // size classes, in increasing extent
+  std::vector<int> ext(np);
+  for (int p = 0; p < np; ++p) ext[p] = class_extent(P->grids[p]);
+  std::vector<int> order(np);
+  for (int p = 0; p < np; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return ext[a] < ext[b]; });
+  for (int p : order) {
+    if (P->classes.empty() || P->classes.back().extent != ext[p]) {
+      bssn_batch_plan::Cls c;
+      c.extent = ext[p];
+      c.variant = -1;
+      for (float& m : c.ms) m = -1.f;
+      P->classes.push_back(c);
+    }
+    P->classes.back().pids.push_back(p);
+  }
+  // device patch records
+  const size_t pbytes = align256(sizeof(Patch) * 4 * size_t(np));
+  // variants a class may use
+  P->var_of_patch.assign(np, VAR_LDS);
+  for (auto& c : P->classes) {
+    bool lds_ok = true;
+    for (int p : c.pids)
+      for (int s = 0; s < 4; ++s)
+        lds_ok = lds_ok && variant_ok(P->hp[s][p], P->order, VAR_LDS);
+    const int dflt = lds_ok ? VAR_LDS : (c.extent > 32 ? VAR_D64 : VAR_D32);
+    c.variant = dflt;
+    if (autotune) {
+      // patch records must be on the device for the trial launches
+      if (!P->dmem) {
+        hipError_t e = hipMalloc((void**)&P->dmem, pbytes);
+        if (e != hipSuccess)
+          return fail(BSSN_ENOMEM, "batch patches: %s", hipGetErrorString(e));
+        for (int s = 0; s < 4; ++s) {
+          e = hipMemcpy(P->dmem + sizeof(Patch) * size_t(s) * np,
+                        P->hp[s].data(), sizeof(Patch) * np,
+                        hipMemcpyHostToDevice);
+          if (e != hipSuccess) return hip_fail(e, "batch patch upload");
+        }
+      }
+      float best = -1.f;
+      for (int v = 0; v < NVAR; ++v) {
+        if (v == VAR_LDS && !lds_ok) continue;
+        int rc = BSSN_OK;
+        const float ms = time_variant(P, c.pids, v, st, &rc);
+        if (rc) return rc;
+        c.ms[v] = ms;
+        if (ms >= 0.f && (best < 0.f || ms < best)) {
+          best = ms;
+          c.variant = v;
+        }
+      }
+    }
+    for (int p : c.pids) P->var_of_patch[p] = c.variant;
+  }
+  // one work list per variant in use, patches in class order
+  std::vector<HostGroup> groups;
+  for (int v = 0; v < NVAR; ++v) {
+    std::vector<int> pids;
+    for (auto& c : P->classes)
+      if (c.variant == v) pids.insert(pids.end(), c.pids.begin(), c.pids.end());
+    if (pids.empty()) continue;
+    groups.emplace_back();
+    int rc = build_group(P->grids, pids, v, persistent_groups(), groups.back());
+    if (rc) return rc;
+  }
+  size_t total = pbytes;
+  for (auto& g : groups) total += group_bytes(g);
+  if (P->dmem) {
+    (void)hipFree(P->dmem);
+    P->dmem = nullptr;
+  }
+  hipError_t e = hipMalloc((void**)&P->dmem, total);
+  if (e != hipSuccess)
+    return fail(BSSN_ENOMEM, "batch work lists (%zu bytes): %s", total,
+                hipGetErrorString(e));
+  for (int s = 0; s < 4; ++s) {
+    e = hipMemcpy(P->dmem + sizeof(Patch) * size_t(s) * np, P->hp[s].data(),
+                  sizeof(Patch) * np, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "batch patch upload");
+  }
+  char* cur = P->dmem + pbytes;
+  for (auto& g : groups) {
+    BatchLaunch L{};
+    e = upload_group(g, cur, L);
+    if (e != hipSuccess) return hip_fail(e, "batch work-list upload");
+    P->launches.push_back(L);
+    cur += group_bytes(g);
+  }
+  return record_graph(P);
+}
+
+}  // namespace
+}  // namespace bssn
+
+extern "C" {
+
+int batch_patches_plan(int npatch, const bssn_grid* grids,
+                       const bssn_params* params, double* const* u,
+                       double* const* a, double* const* b,
+                       double* const* acc, double dt, int autotune,
+                       bssn_batch_plan** plan, void* stream) {
+  if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  int rc = check_params(params);
+  if (rc) return rc;
+  if (npatch < 1 || npatch > kMaxPatches)
+    return fail(BSSN_EINVAL, "npatch = %d outside 1..%d", npatch, kMaxPatches);
+  if (!grids || !u || !a || !b || !acc)
+    return fail(BSSN_EINVAL, "grids and the buffer arrays must be non-NULL");
+  if (!std::isfinite(dt)) return fail(BSSN_EINVAL, "dt is not finite");
+  if (autotune != 0 && autotune != 1)
+    return fail(BSSN_EINVAL, "autotune = %d (0 or 1)", autotune);
+  for (int p = 0; p < npatch; ++p) {
+    if ((rc = check_grid(&grids[p], params->fd_order)))
+      return fail(rc, "patch %d: %s", p, bssn_last_error());
+    if (grids[p].bc != BSSN_BC_STATIC)
+      return fail(BSSN_EINVAL, "patch %d: batched patches need "
+                  "BSSN_BC_STATIC", p);
+    const double* q[4] = {u[p], a[p], b[p], acc[p]};
+    for (int i = 0; i < 4; ++i) {
+      if (!q[i]) return fail(BSSN_EINVAL, "patch %d: buffer %d is NULL", p, i);
+      for (int j = 0; j < i; ++j)
+        if (q[i] == q[j])
+          return fail(BSSN_EINVAL, "patch %d: buffers %d and %d alias", p, j, i);
+    }
+  }
+  bssn_batch_plan* P = new (std::nothrow) bssn_batch_plan();
+  if (!P) return fail(BSSN_ENOMEM, "batch plan");
+  hipError_t e = hipGetDevice(&P->device);
+  if (e != hipSuccess) {
+    delete P;
+    return hip_fail(e, "hipGetDevice");
+  }
+  P->order = params->fd_order;
+  P->precision = params->precision;
+  P->np = npatch;
+  P->G = make_gauge(params);
+  P->grids.assign(grids, grids + npatch);
+  // stage s reads u_s, writes out (rk4_stage semantics): u -> a -> b -> a -> u
+  for (int s = 0; s < 4; ++s) P->hp[s].resize(npatch);
+  for (int p = 0; p < npatch; ++p) {
+    Patch base = make_patch(&grids[p]);
+    base.dt = dt;
+    base.u_n = u[p];
+    base.acc = acc[p];
+    const double* us[4] = {u[p], a[p], b[p], a[p]};
+    double* out[4] = {a[p], b[p], a[p], u[p]};
+    for (int s = 0; s < 4; ++s) {
+      Patch q = base;
+      q.u_s = us[s];
+      q.out = out[s];
+      P->hp[s][p] = q;
+    }
+    const void* bufs[4] = {u[p], a[p], b[p], acc[p]};
+    for (const void* ptr : bufs) {
+      AddrRange r{};
+      e = hipMemGetAddressRange(&r.base, &r.size, (hipDeviceptr_t)ptr);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete P;
+        return fail(BSSN_EINVAL, "patch %d: a buffer is not device memory "
+                    "of this device", p);
+      }
+      P->ptrs.push_back(ptr);
+      P->ranges.push_back(r);
+    }
+  }
+  rc = plan_build(P, autotune, (hipStream_t)stream);
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  *plan = P;
+  return BSSN_OK;
+}
+
+int batch_patches(bssn_batch_plan* plan, int nsteps, void* stream) {
+  if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
+  if (nsteps < 0) return fail(BSSN_EINVAL, "nsteps = %d < 0", nsteps);
+  int rc = check_fresh(plan);
+  if (rc) return rc;
+  for (int k = 0; k < nsteps; ++k) {
+    hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  }
+  return BSSN_OK;
+}
+
+int batch_patches_unbatched(bssn_batch_plan* plan, int nsteps, void* stream) {
+  if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
+  if (nsteps < 0) return fail(BSSN_EINVAL, "nsteps = %d < 0", nsteps);
+  int rc = check_fresh(plan);
+  if (rc) return rc;
+  const int nwg = persistent_groups();
+  for (int k = 0; k < nsteps; ++k)
+    for (int s = 0; s < 4; ++s)
+      for (int p = 0; p < plan->np; ++p) {
+        hipError_t e = launch_patch(plan->hp[s][p], plan->G, plan->order, s,
+                                    plan->precision, plan->var_of_patch[p],
+                                    nwg, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "per-patch stage launch");
+      }
+  return BSSN_OK;
+}
+
+int batch_patches_describe(const bssn_batch_plan* plan, int max_classes,
+                           int32_t* out) {
+  if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
+  if (max_classes < 0 || (max_classes > 0 && !out))
+    return fail(BSSN_EINVAL, "out must hold 3 * max_classes entries");
+  const int n = int(plan->classes.size());
+  for (int i = 0; i < n && i < max_classes; ++i) {
+    const auto& c = plan->classes[i];
+    out[3 * i] = c.extent;
+    if (c.variant == VAR_LDS) {
+      out[3 * i + 1] = kLdsTile[0];
+      out[3 * i + 2] = kLdsTile[1];
+    } else {
+      out[3 * i + 1] = kDirectBX[c.variant];
+      out[3 * i + 2] = 256 / kDirectBX[c.variant];
+    }
+  }
+  return n;
+}
+
+int batch_patches_destroy(bssn_batch_plan* plan) {
+  delete plan;
+  return BSSN_OK;
+}
+
+}  // extern "C"

@@ -422,7 +422,7 @@ __global__ void __launch_bounds__(256)
 }
 
 void tile_grid(const Patch& P, dim3& grd, dim3& blk) {
-  stage_tile_shape(P, blk);
+  stage_tile_shape(P, 0, blk);
   grd = dim3((P.n[0] + blk.x - 1) / blk.x, (P.n[1] + blk.y - 1) / blk.y,
              P.n[2]);
 }

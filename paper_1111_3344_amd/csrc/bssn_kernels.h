@@ -29,6 +29,50 @@ inline hipError_t launch_stage(const Patch& P, const Gauge& G, int order,
              : launch_stage_o4(P, G, periodic, stage, precision, path, nwg, st);
 }
 
+// One static patch with an explicit kernel variant (VAR_*); nwg bounds the
+// persistent launch of VAR_LDS.
+hipError_t launch_patch_o4(const Patch& P, const Gauge& G, int stage,
+                           int precision, int variant, int nwg,
+                           hipStream_t st);
+hipError_t launch_patch_o8(const Patch& P, const Gauge& G, int stage,
+                           int precision, int variant, int nwg,
+                           hipStream_t st);
+// Whether the layout of P (every buffer it names) allows the variant.
+bool variant_ok_o4(const Patch& P, int variant);
+bool variant_ok_o8(const Patch& P, int variant);
+
+// One batched launch over device work lists.  VAR_LDS: items are LdsItem,
+// workgroup q runs items [wstart[q], wstart[q+1]), nwg workgroups.  VAR_D*:
+// items are DirectItem, one workgroup per item.
+struct BatchLaunch {
+  int variant;
+  const Patch* patches;   // device, indexed by item.patch
+  const void* items;      // device
+  const int32_t* wstart;  // device, nwg + 1 entries (VAR_LDS)
+  int nitems;
+  int nwg;
+};
+hipError_t launch_batch_o4(const BatchLaunch& B, const Gauge& G, int stage,
+                           int precision, hipStream_t st);
+hipError_t launch_batch_o8(const BatchLaunch& B, const Gauge& G, int stage,
+                           int precision, hipStream_t st);
+inline hipError_t launch_patch(const Patch& P, const Gauge& G, int order,
+                               int stage, int precision, int variant,
+                               int nwg, hipStream_t st) {
+  return order == 8
+             ? launch_patch_o8(P, G, stage, precision, variant, nwg, st)
+             : launch_patch_o4(P, G, stage, precision, variant, nwg, st);
+}
+inline bool variant_ok(const Patch& P, int order, int variant) {
+  return order == 8 ? variant_ok_o8(P, variant) : variant_ok_o4(P, variant);
+}
+inline hipError_t launch_batch(const BatchLaunch& B, const Gauge& G,
+                               int order, int stage, int precision,
+                               hipStream_t st) {
+  return order == 8 ? launch_batch_o8(B, G, stage, precision, st)
+                    : launch_batch_o4(B, G, stage, precision, st);
+}
+
 // Constraint fields and norms (see bssn_constraints in bssn.h).
 struct ConstraintArgs {
   const double* u;

@@ -53,6 +53,12 @@ struct TileGeo<8> {
   static constexpr int BUFD = L * 256 * 2;
 };
 
+static_assert(TileGeo<4>::TX == kLdsTile[0] && TileGeo<4>::TY == kLdsTile[1] &&
+                  TileGeo<4>::TZ == kLdsTile[2] &&
+                  TileGeo<8>::TX == kLdsTile[0] &&
+                  TileGeo<8>::TY == kLdsTile[1] && TileGeo<8>::TZ == kLdsTile[2],
+              "host work lists assume the kLdsTile shape");
+
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef __attribute__((address_space(3))) double lds_double;
 
@@ -273,24 +279,22 @@ __host__ __device__ __forceinline__ void walk_range(int lin, int nwg,
   hi = int((int64_t(ntiles) * (lin + 1)) / nwg);
 }
 
-// MIXED = false: FP64 everywhere.  MIXED = true: per tile, FP32 stencils and
-// algebra unless the tile's minimum lapse is below G.alpha_thr (then FP64);
-// the branch is uniform over the workgroup.
+// Tiles [tlo, thi) of patch P (numbered as in TileMap), pipelined through
+// the workgroup's LDS ring.  MIXED = false: FP64 everywhere.  MIXED = true:
+// per tile, FP32 stencils and algebra unless the tile's minimum lapse is
+// below G.alpha_thr (then FP64); the branch is uniform over the workgroup.
+// On return every DMA of this call has landed; the caller places a barrier
+// before the ring is filled again.
 template <int ORDER, bool MIXED>
-__global__ void __launch_bounds__(256)
-    k_stage_lds(const Patch P, const Gauge G, const int stage,
-                const TileMap M) {
+__device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
+                                          const int stage, const TileMap& M,
+                                          const int tlo, const int thi,
+                                          double* ring, double* sc) {
   using Geo = TileGeo<ORDER>;
-  __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
-  __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
-
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int tx = lane & 15, ty = lane >> 4, tz = wave;
-  const int nwg = gridDim.x;
-  int tlo, thi;
-  walk_range(walk_pos(blockIdx.x, nwg), nwg, M.ntiles, tlo, thi);
   const int ntile_mine = thi - tlo;
   if (ntile_mine <= 0) return;
 
@@ -373,8 +377,49 @@ __global__ void __launch_bounds__(256)
       dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
     }
   }
-  // drain outstanding DMA before the workgroup retires
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  // drain outstanding DMA (the last tile prefetched a next one that is not
+  // used) and this wave's LDS reads
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+}
+
+// One patch: workgroup b takes the tiles of position walk_pos(b).
+template <int ORDER, bool MIXED>
+__global__ void __launch_bounds__(256)
+    k_stage_lds(const Patch P, const Gauge G, const int stage,
+                const TileMap M) {
+  using Geo = TileGeo<ORDER>;
+  __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
+  __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  const int nwg = gridDim.x;
+  int tlo, thi;
+  walk_range(walk_pos(blockIdx.x, nwg), nwg, M.ntiles, tlo, thi);
+  lds_tiles<ORDER, MIXED>(P, G, stage, M, tlo, thi, ring, sc);
+}
+
+// Many patches: workgroup b runs the items [wstart[q], wstart[q+1]) for
+// q = walk_pos(b).
+template <int ORDER, bool MIXED>
+__global__ void __launch_bounds__(256)
+    k_stage_lds_batch(const Patch* __restrict__ patches,
+                      const LdsItem* __restrict__ items,
+                      const int32_t* __restrict__ wstart, const Gauge G,
+                      const int stage) {
+  using Geo = TileGeo<ORDER>;
+  __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
+  __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  const int q = walk_pos(blockIdx.x, gridDim.x);
+  const int i0 = wstart[q], i1 = wstart[q + 1];
+  for (int i = i0; i < i1; ++i) {
+    const LdsItem it = items[i];
+    const Patch P = patches[it.patch];
+    TileMap M;
+    M.ntx = it.ntx;
+    M.nty = it.nty;
+    M.ntz = it.ntz;
+    M.ntiles = it.ntx * it.nty * it.ntz;
+    lds_tiles<ORDER, MIXED>(P, G, stage, M, it.tlo, it.thi, ring, sc);
+    __builtin_amdgcn_s_barrier();  // every wave is done with ring and sc
+  }
 }
 
 template <int ORDER>
@@ -415,6 +460,57 @@ hipError_t launch_stage_lds(const Patch& P, const Gauge& G, int stage,
     hipLaunchKernelGGL((k_stage_lds<ORDER, true>), dim3(nwg), dim3(256), 0,
                        st, P, G, stage, M);
   return hipGetLastError();
+}
+
+// Explicit-variant launch of one static patch, and batched launches.
+template <int ORDER>
+hipError_t launch_patch_t(const Patch& P, const Gauge& G, int stage,
+                          int precision, int variant, int nwg,
+                          hipStream_t st) {
+  switch (variant) {
+    case VAR_LDS:
+      return launch_stage_lds<ORDER>(P, G, stage, precision, nwg, st);
+    case VAR_D64:
+      return launch_stage_variant<ORDER, false>(P, G, stage, precision, 64,
+                                                st);
+    case VAR_D32:
+      return launch_stage_variant<ORDER, false>(P, G, stage, precision, 32,
+                                                st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int ORDER>
+bool variant_ok_t(const Patch& P, int variant) {
+  if (variant != VAR_LDS) return variant == VAR_D64 || variant == VAR_D32;
+  Patch q = P;
+  const double* bufs[4] = {P.u_s, P.u_n, P.acc, P.out};
+  for (const double* b : bufs) {
+    if (!b) continue;
+    q.u_s = b;
+    if (!lds_path_ok<ORDER>(q)) return false;
+  }
+  return true;
+}
+
+template <int ORDER>
+hipError_t launch_batch_t(const BatchLaunch& B, const Gauge& G, int stage,
+                          int precision, hipStream_t st) {
+  if (B.variant == VAR_LDS) {
+    const LdsItem* it = static_cast<const LdsItem*>(B.items);
+    if (precision == 0)
+      hipLaunchKernelGGL((k_stage_lds_batch<ORDER, false>), dim3(B.nwg),
+                         dim3(256), 0, st, B.patches, it, B.wstart, G, stage);
+    else
+      hipLaunchKernelGGL((k_stage_lds_batch<ORDER, true>), dim3(B.nwg),
+                         dim3(256), 0, st, B.patches, it, B.wstart, G, stage);
+    return hipGetLastError();
+  }
+  if (B.variant != VAR_D64 && B.variant != VAR_D32)
+    return hipErrorInvalidValue;
+  return launch_direct_batch<ORDER>(
+      B.patches, static_cast<const DirectItem*>(B.items), B.nitems,
+      B.variant == VAR_D64 ? 64 : 32, G, stage, precision, st);
 }
 
 }  // namespace bssn

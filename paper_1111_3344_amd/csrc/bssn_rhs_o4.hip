@@ -11,8 +11,19 @@ hipError_t launch_stage_o4(const Patch& P, const Gauge& G, int periodic,
   const bool lds = !periodic && path != PATH_DIRECT && lds_path_ok<4>(P);
   if (lds) return launch_stage_lds<4>(P, G, stage, precision, nwg, st);
   return periodic
-             ? launch_stage_variant<4, true>(P, G, stage, precision, st)
-             : launch_stage_variant<4, false>(P, G, stage, precision, st);
+             ? launch_stage_variant<4, true>(P, G, stage, precision, 0, st)
+             : launch_stage_variant<4, false>(P, G, stage, precision, 0,
+                                                   st);
+}
+
+hipError_t launch_patch_o4(const Patch& P, const Gauge& G, int stage,
+                           int precision, int variant, int nwg,
+                           hipStream_t st) {
+  return launch_patch_t<4>(P, G, stage, precision, variant, nwg, st);
+}
+
+bool variant_ok_o4(const Patch& P, int variant) {
+  return variant_ok_t<4>(P, variant);
 }
 
 }  // namespace bssn

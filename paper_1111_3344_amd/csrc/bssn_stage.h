@@ -212,12 +212,13 @@ __device__ __forceinline__ void stage_point(const Patch& P, const Gauge& G,
   epilogue<T>(P, stage, r, vc, nbytes);
 }
 
+// The point (x, y, z) of a workgroup-shaped tile; TILES selects which tiles
+// a mixed-precision kernel of a pair takes (the predicate is uniform over
+// the workgroup).
 template <int ORDER, bool PERIODIC, int TILES>
-__global__ void __launch_bounds__(256)
-    k_stage(const Patch P, const Gauge G, const int stage) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
+__device__ __forceinline__ void stage_block(const Patch& P, const Gauge& G,
+                                            const int stage, int x, int y,
+                                            int z) {
   const bool active = x < P.n[0] && y < P.n[1];
   if constexpr (TILES != TILE_ALL) {
     const int g = P.ghost;
@@ -235,17 +236,40 @@ __global__ void __launch_bounds__(256)
     stage_point<ORDER, PERIODIC, double>(P, G, stage, x, y, z);
 }
 
+// One patch: block (bx, by) of z-plane z covers x in [bx*BX, bx*BX + BX).
+template <int ORDER, bool PERIODIC, int TILES>
+__global__ void __launch_bounds__(256)
+    k_stage(const Patch P, const Gauge G, const int stage) {
+  stage_block<ORDER, PERIODIC, TILES>(
+      P, G, stage, blockIdx.x * blockDim.x + threadIdx.x,
+      blockIdx.y * blockDim.y + threadIdx.y, blockIdx.z);
+}
+
+// Many static patches: block b takes work item b = (patch, x0, y0, z).
+template <int ORDER, int TILES>
+__global__ void __launch_bounds__(256)
+    k_stage_direct_batch(const Patch* __restrict__ patches,
+                         const DirectItem* __restrict__ work, const Gauge G,
+                         const int stage) {
+  const DirectItem w = work[blockIdx.x];
+  const Patch P = patches[w.patch];
+  stage_block<ORDER, false, TILES>(P, G, stage, w.x0 + threadIdx.x,
+                                   w.y0 + threadIdx.y, w.z);
+}
+
 // ---- host-side launch -------------------------------------------------------------
-inline void stage_tile_shape(const Patch& P, dim3& blk) {
-  const int bx = P.n[0] > 32 ? 64 : 32;
+// Workgroup shape of the direct kernel: bx x (256 / bx); bx = 0 picks it
+// from the patch width.
+inline void stage_tile_shape(const Patch& P, int bx, dim3& blk) {
+  if (bx <= 0) bx = P.n[0] > 32 ? 64 : 32;
   blk = dim3(bx, 256 / bx, 1);
 }
 
 template <int ORDER, bool PERIODIC>
 hipError_t launch_stage_variant(const Patch& P, const Gauge& G, int stage,
-                                int precision, hipStream_t st) {
+                                int precision, int bx, hipStream_t st) {
   dim3 blk;
-  stage_tile_shape(P, blk);
+  stage_tile_shape(P, bx, blk);
   dim3 grd((P.n[0] + blk.x - 1) / blk.x, (P.n[1] + blk.y - 1) / blk.y, P.n[2]);
   if (precision == 0) {
     hipLaunchKernelGGL((k_stage<ORDER, PERIODIC, TILE_ALL>), grd, blk, 0, st,
@@ -255,6 +279,23 @@ hipError_t launch_stage_variant(const Patch& P, const Gauge& G, int stage,
                        P, G, stage);
     hipLaunchKernelGGL((k_stage<ORDER, PERIODIC, TILE_FP64>), grd, blk, 0, st,
                        P, G, stage);
+  }
+  return hipGetLastError();
+}
+
+template <int ORDER>
+hipError_t launch_direct_batch(const Patch* patches, const DirectItem* work,
+                               int nwork, int bx, const Gauge& G, int stage,
+                               int precision, hipStream_t st) {
+  const dim3 blk(bx, 256 / bx, 1);
+  if (precision == 0) {
+    hipLaunchKernelGGL((k_stage_direct_batch<ORDER, TILE_ALL>), dim3(nwork),
+                       blk, 0, st, patches, work, G, stage);
+  } else {
+    hipLaunchKernelGGL((k_stage_direct_batch<ORDER, TILE_FP32>), dim3(nwork),
+                       blk, 0, st, patches, work, G, stage);
+    hipLaunchKernelGGL((k_stage_direct_batch<ORDER, TILE_FP64>), dim3(nwork),
+                       blk, 0, st, patches, work, G, stage);
   }
   return hipGetLastError();
 }

@@ -106,3 +106,35 @@ def test_constraints_validation():
 def test_periodic_grid_must_cover_stencil():
     g = I.GridSpec((2, 8, 8), 3, (0.1,) * 3, (0,) * 3, I.BC_PERIODIC)
     assert _stage(B.c_grid(g), B.Params().c()) == B.BSSN_EINVAL
+
+
+def _plan(grids, prm, bufs=None, dt=0.1, autotune=0, out=True):
+    n = len(grids)
+    G = (B.bssn_grid * max(1, n))(*[B.c_grid(g) for g in grids])
+    if bufs is None:
+        bufs = [[8 * (4 * p + i + 1) for p in range(n)] for i in range(4)]
+    arrs = [(ctypes.c_void_p * max(1, n))(*b) for b in bufs]
+    h = ctypes.c_void_p()
+    return B.lib().batch_patches_plan(n, G, ctypes.byref(prm), *arrs, dt,
+                                      autotune,
+                                      ctypes.byref(h) if out else None, None)
+
+
+def test_batch_plan_validation():
+    g = I.cell_centred(8, -1, 1, 3)
+    prm = B.Params().c()
+    assert _plan([], prm) == B.BSSN_EINVAL
+    assert _plan([g], prm, out=False) == B.BSSN_EINVAL
+    assert _plan([g], prm, dt=float("inf")) == B.BSSN_EINVAL
+    assert _plan([g], prm, autotune=2) == B.BSSN_EINVAL
+    gp = I.cell_centred(8, -1, 1, 3, I.BC_PERIODIC)
+    assert _plan([g, gp], prm) == B.BSSN_EINVAL
+    assert "patch 1" in B.bssn_last_error()
+    assert _plan([g], prm, bufs=[[8], [8], [16], [24]]) == B.BSSN_EINVAL
+    assert "alias" in B.bssn_last_error()
+    assert _plan([g], prm, bufs=[[8], [0], [16], [24]]) == B.BSSN_EINVAL
+    assert _plan([g], B.Params(fd_order=8).c()) == B.BSSN_EINVAL
+    L = B.lib()
+    assert L.batch_patches(None, 1, None) == B.BSSN_EINVAL
+    assert L.batch_patches_unbatched(None, 1, None) == B.BSSN_EINVAL
+    assert L.batch_patches_describe(None, 0, None) == B.BSSN_EINVAL

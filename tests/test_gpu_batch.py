@@ -1,0 +1,156 @@
+"""Many uneven static patches advanced together (batch_patches) through the
+C ABI (needs an MI355X).
+
+  * batched == per-patch launches of the same kernel variants, bitwise, for
+    FP64 and mixed precision, orders 4 and 8 (a race or halo-bookkeeping
+    mistake in the work list shows up as a bit difference);
+  * batched with the LDS variant == rk4_stage on each patch, bitwise;
+  * every patch after one batched step == the oracle's RK4 step, within the
+    state tolerance of the single-patch parity tests;
+  * a plan whose buffer was freed reports BSSN_ESTALE and launches nothing.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1111_3344_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1111_3344_amd import bssn
+    bssn.lib()
+    bssn.bssn_set_path(bssn.BSSN_PATH_AUTO)
+    return bssn
+
+
+def host_set(n, seed, nlo, nhi, order=4):
+    specs = I.patches(n, seed=seed, nlo=nlo, nhi=nhi,
+                      ghost=3 if order == 4 else 5)
+    grids = [g for g, _, _ in specs]
+    us = [I.brill_lindquist(g, (m,), (c,)) for g, m, c in specs]
+    return grids, us
+
+
+def device_set(B, us):
+    u = [B.to_device(x) for x in us]
+    return (u, [t.clone() for t in u], [t.clone() for t in u],
+            [torch.zeros_like(t) for t in u])
+
+
+def reset(bufs, us):
+    u, a, b, acc = bufs
+    for i, x in enumerate(us):
+        src = torch.from_numpy(x).to("cuda")
+        u[i].copy_(src)
+        a[i].copy_(src)
+        b[i].copy_(src)
+        acc[i].zero_()
+    torch.cuda.synchronize()
+
+
+def results(grids, u):
+    torch.cuda.synchronize()
+    return [g.interior(t.cpu().numpy()).copy() for g, t in zip(grids, u)]
+
+
+@pytest.mark.parametrize("order,precision,autotune", [
+    (4, 0, 1), (4, 1, 1), (4, 0, 0), (8, 0, 1), (8, 1, 0)])
+def test_batched_equals_per_patch_bitwise(B, order, precision, autotune):
+    grids, us = host_set(9, 41 + order + precision, 17, 61, order)
+    bufs = device_set(B, us)
+    prm = B.Params(fd_order=order, precision=precision)
+    dt = 0.25 * 0.125
+    plan = B.batch_patches_plan(grids, prm, *bufs, dt, autotune=autotune)
+    reset(bufs, us)  # autotuning ran stage 0 into a and acc
+    B.batch_patches(plan, 2)
+    got = results(grids, bufs[0])
+    reset(bufs, us)
+    B.batch_patches_unbatched(plan, 2)
+    ref = results(grids, bufs[0])
+    for p, (x, y) in enumerate(zip(got, ref)):
+        assert np.array_equal(x, y), f"patch {p} differs"
+        assert np.isfinite(x).all()
+    plan.destroy()
+
+
+def test_batched_lds_equals_rk4_stage_bitwise(B):
+    grids, us = host_set(7, 57, 20, 58)
+    bufs = device_set(B, us)
+    prm = B.Params()
+    dt = 0.03125
+    plan = B.batch_patches_plan(grids, prm, *bufs, dt, autotune=0)
+    classes = B.batch_patches_describe(plan)
+    assert all((tx, ty) == (16, 4) for _, tx, ty in classes)
+    B.batch_patches(plan, 1)
+    got = results(grids, bufs[0])
+    for p, (g, x) in enumerate(zip(grids, us)):
+        du = B.to_device(x)
+        a, b, acc = du.clone(), du.clone(), torch.zeros_like(du)
+        B.rk4_step(g, prm, dt, du, a, b, acc)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[p], g.interior(du.cpu().numpy())), p
+    plan.destroy()
+
+
+def test_batched_matches_oracle(B):
+    grids, us = host_set(5, 77, 18, 34)
+    bufs = device_set(B, us)
+    prm = B.Params()
+    dt = 0.03125
+    plan = B.batch_patches_plan(grids, prm, *bufs, dt, autotune=1)
+    reset(bufs, us)
+    B.batch_patches(plan, 1)
+    got = results(grids, bufs[0])
+    for p, (g, x) in enumerate(zip(grids, us)):
+        ref = g.interior(O.rk4_step(g, O.params(), dt, x))
+        u0 = g.interior(x)
+        d = np.abs(ref - u0).reshape(25, -1).max(1)
+        m = np.abs(ref).reshape(25, -1).max(1)
+        tol = 1e-12 * d + 8 * EPS * np.maximum(m, 1e-300)
+        err = np.abs(got[p] - ref).reshape(25, -1).max(1)
+        assert (err <= tol).all(), (p, err / np.maximum(tol, 1e-300))
+    plan.destroy()
+
+
+def test_describe_classes(B):
+    grids, us = host_set(12, 91, 17, 90)
+    bufs = device_set(B, us)
+    plan = B.batch_patches_plan(grids, B.Params(), *bufs, 0.03, autotune=1)
+    classes = B.batch_patches_describe(plan)
+    ext = [c[0] for c in classes]
+    assert ext == sorted(set(ext))
+    want = sorted({(max(g.n) + 15) // 16 * 16 for g in grids})
+    assert ext == want
+    assert all((tx, ty) in ((16, 4), (64, 4), (32, 8)) for _, tx, ty in classes)
+    assert B.batch_patches_describe(plan, max_classes=1)[0] == classes[0]
+    plan.destroy()
+
+
+def test_stale_plan_after_free(B):
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    grids, us = host_set(2, 5, 17, 20)
+    u, a, b, acc = device_set(B, us)
+    raw = ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(raw), grids[1].total * 8) == 0
+    acc = [acc[0], raw.value]
+    plan = B.batch_patches_plan(grids, B.Params(), u, a, b, acc, 0.03,
+                                autotune=0)
+    torch.cuda.synchronize()
+    assert hip.hipFree(raw) == 0
+    for fn in (B.batch_patches, B.batch_patches_unbatched):
+        with pytest.raises(B.BssnError) as ei:
+            fn(plan, 1)
+        assert ei.value.code == B.BSSN_ESTALE
+    plan.destroy()
