@@ -8,6 +8,19 @@ HBM, bracketed by device synchronisations; HIP events recorded on the launch
 stream around every stage give the average kernel duration used for the
 roofline.  Prints ONE JSON line.
 
+Profiling support (the summaries under profiles/ are made this way):
+    rocprofv3 --kernel-trace --stats --output-format csv -d D -o run \
+        -- python bench.py                      # kernel durations
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d D -o run \
+        -- python bench.py --steps 2 --warmup 0 --no-cpu-baseline \
+           --no-mixed --calibrate-copy          # then WRITE_SIZE alike
+    python bench.py --summarize-profile D1 D2 ... > profiles/<name>.txt
+--calibrate-copy ends the run with three plain device-to-device copies of
+1 GiB, so the HBM byte counters can be scaled by what they read for a copy
+of known size.  The roofline's `traffic` is taken from
+profiles/traffic_<kernel>_<workload>.txt when the kernel sources still
+hash to the value recorded there, else it is null.
+
 Algorithmic HBM bytes per interior point (25 FP64 slots = 200 B per state):
 stage 0: read u_n, write acc and u_out = 600 B; stages 1, 2: read u_s, u_n,
 acc, write acc, u_out = 1000 B; stage 3: read u_s, acc, write u_out = 600 B;
@@ -88,40 +101,190 @@ def time_gpu(B, torch, g, u_host, prm, dt, steps, warmup):
     return wall, per_stage
 
 
-def cpu_baseline(name, seconds_target=15.0):
+def cpu_baseline(name, target_s=15.0):
     """The oracle on the host cores over a bounded sample of the workload:
     a z-slab of the same grid (same data, static ghosts taken from the full
-    grid), one classical RK4 step."""
+    grid), whole RK4 steps.  A probe slab of two planes per thread (the
+    oracle's loops are parallel over planes) sets the slab thickness (and,
+    when the whole grid is quicker than target_s, the step count) so that
+    the sample takes about target_s."""
     import numpy as np
     from oracle import oracle as O
     from paper_1111_3344_amd import inputs as I
     n, lo, hi, gh, masses, centres, order, dt, desc = WORKLOADS[name]
     h = (hi - lo) / n
-    # slab thickness chosen so the sample is ~10-30 s of CPU work
-    t0 = time.perf_counter()
-    probe = I.GridSpec((n, n, 1), gh, (h, h, h),
-                       (lo + 0.5 * h,) * 2 + (lo + 0.5 * h + (n // 2) * h,),
-                       I.BC_STATIC)
-    up = (I.brill_lindquist(probe, masses, centres) if masses else
-          I.minkowski_noise(probe))
     prm = O.params(fd_order=order)
-    O.rk4_step(probe, prm, dt, up)
-    t_plane = time.perf_counter() - t0
-    nz = int(max(1, min(n, seconds_target / max(t_plane, 1e-3))))
-    z0 = n // 2 - nz // 2
-    g = I.GridSpec((n, n, nz), gh, (h, h, h),
-                   (lo + 0.5 * h, lo + 0.5 * h, lo + 0.5 * h + z0 * h),
-                   I.BC_STATIC)
-    u = (I.brill_lindquist(g, masses, centres) if masses else
-         I.minkowski_noise(g))
+
+    def slab(nz):
+        z0 = n // 2 - nz // 2
+        g = I.GridSpec((n, n, nz), gh, (h, h, h),
+                       (lo + 0.5 * h, lo + 0.5 * h, lo + 0.5 * h + z0 * h),
+                       I.BC_STATIC)
+        u = (I.brill_lindquist(g, masses, centres) if masses else
+             I.minkowski_noise(g))
+        return g, u
+
+    g, u = slab(min(n, 2 * O.num_threads()))
+    O.rk4_step(g, prm, dt, u)  # thread start-up outside the probe
     t0 = time.perf_counter()
     O.rk4_step(g, prm, dt, u)
+    rate = g.npoints / (time.perf_counter() - t0)
+    nz = int(max(1, min(n, round(target_s * rate / (n * n)))))
+    steps = 1
+    if nz == n:
+        steps = int(max(1, round(target_s * rate / (n * n * n))))
+    g, u = slab(nz)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u = O.rk4_step(g, prm, dt, u)
     t = time.perf_counter() - t0
-    pts = g.npoints
+    pts = g.npoints * steps
     return {"value": pts / t, "unit": "grid-point updates/s",
             "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"one RK4 step on a {n}x{n}x{nz} z-slab of {name} "
-                      f"({pts} points, {t:.1f} s)"}
+            "sample": f"{steps} RK4 step(s) of the FP64 oracle on a "
+                      f"{n}x{n}x{nz} z-slab of {name} ({pts} point updates, "
+                      f"{t:.1f} s)"}
+
+
+# ---- rocprofv3 summaries ------------------------------------------------------
+KERNEL_SOURCES = ("bssn_internal.h", "bssn_point.h", "bssn_stage.h",
+                  "bssn_lds.h", "bssn_rhs_o4.hip", "bssn_rhs_o8.hip")
+CALIB_BYTES = 1 << 30
+
+
+def kernel_source_hash():
+    import hashlib
+    hsh = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1111_3344_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()[:16]
+
+
+def calibrate_copy(torch):
+    """Three plain device-to-device copies of CALIB_BYTES, last in the run."""
+    a = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_profile(dirs, order=4):
+    """Text summary of rocprofv3 CSV output directories: per-kernel dispatch
+    durations (kernel trace) and per-dispatch counter values (pmc runs).
+    Lines starting with '#' are the summary; the 'key: value' lines at the
+    end are the figures bench.py reads back for the FP64 stage kernel of the
+    given order (HBM bytes per launch scaled by the copy calibration, VALU
+    FLOPs per launch), stamped with the hash of the kernel sources."""
+    import glob
+    import collections
+    import re
+    out = []
+    stage = re.compile(r"k_stage_lds<\s*%d\s*,\s*false\s*>" % order)
+    kv = {}
+    for d in dirs:
+        for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"),
+                                  recursive=True)):
+            dur = collections.defaultdict(list)
+            for r in _csv_rows(f):
+                dur[r["Kernel_Name"]].append(
+                    int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+            out.append(f"# kernel trace: {os.path.relpath(f, d)}")
+            out.append("#  calls    avg_us    min_us    max_us  total_ms  "
+                       "kernel")
+            for k, v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+                out.append(f"# {len(v):6d} {sum(v) / len(v) / 1e3:9.1f} "
+                           f"{min(v) / 1e3:9.1f} {max(v) / 1e3:9.1f} "
+                           f"{sum(v) / 1e6:9.2f}  {k[:110]}")
+                if stage.search(k):
+                    kv["avg_launch_us"] = f"{sum(v) / len(v) / 1e3:.2f}"
+        for f in sorted(glob.glob(os.path.join(d, "**",
+                                               "*counter_collection.csv"),
+                                  recursive=True)):
+            per = collections.defaultdict(dict)
+            names = {}
+            for r in _csv_rows(f):
+                did = int(r["Dispatch_Id"])
+                per[did][r["Counter_Name"]] = (
+                    per[did].get(r["Counter_Name"], 0.0) +
+                    float(r["Counter_Value"]))
+                names[did] = r["Kernel_Name"]
+            out.append(f"# counters: {os.path.relpath(f, d)}")
+            agg = collections.defaultdict(lambda: collections.defaultdict(list))
+            for did in sorted(per):
+                for c, v in per[did].items():
+                    agg[names[did]][c].append(v)
+            for k, cs in agg.items():
+                for c, v in cs.items():
+                    out.append(f"#   {c:26s} dispatches {len(v):4d} avg "
+                               f"{sum(v) / len(v):14.6g}  {k[:90]}")
+                    if stage.search(k):
+                        kv[f"{c}_per_launch"] = sum(v) / len(v)
+            copies = [did for did in sorted(per)
+                      if "copyBuffer" in names[did]][-3:]
+            for c in sorted({c for did in copies for c in per[did]}):
+                v = [per[did][c] for did in copies]
+                out.append(f"#   calibration: {c} over {len(v)} plain "
+                           f"copies of {CALIB_BYTES} bytes, avg "
+                           f"{sum(v) / len(v):.6g}")
+                kv[f"copy_{c}"] = sum(v) / len(v)
+    res = [f"source_sha256: {kernel_source_hash()}"]
+    if "avg_launch_us" in kv:
+        res.append(f"avg_launch_us: {kv['avg_launch_us']}")
+    if all(k in kv for k in ("FETCH_SIZE_per_launch", "WRITE_SIZE_per_launch",
+                             "copy_FETCH_SIZE", "copy_WRITE_SIZE")):
+        res += [f"fetch_kib_per_launch: {kv['FETCH_SIZE_per_launch']:.6g}",
+                f"write_kib_per_launch: {kv['WRITE_SIZE_per_launch']:.6g}",
+                f"copy_bytes: {CALIB_BYTES}",
+                f"copy_fetch_kib: {kv['copy_FETCH_SIZE']:.6g}",
+                f"copy_write_kib: {kv['copy_WRITE_SIZE']:.6g}"]
+    for prec in ("F64", "F32"):
+        parts = [f"SQ_INSTS_VALU_{o}_{prec}_per_launch"
+                 for o in ("ADD", "MUL", "FMA", "TRANS")]
+        if all(p in kv for p in parts):
+            a, m, fma, tr = (kv[p] for p in parts)
+            res.append(f"valu_flops_{prec.lower()}_per_launch: "
+                       f"{64 * (a + m + tr + 2 * fma):.6g}")
+    return "\n".join(out + res)
+
+
+def profile_figures(workload, kernel_tag):
+    """The key: value figures of the committed counter summary for this
+    kernel and workload, or (None, reason) when there is none or the kernel
+    sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles",
+                        f"traffic_{kernel_tag}_{workload}.txt")
+    if not os.path.exists(path):
+        return None, "no counter summary for this workload"
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    return kv, os.path.relpath(path, ROOT)
+
+
+def traffic_bytes(kv):
+    """Measured HBM bytes per stage launch: each counter scaled by what it
+    reads for a plain copy of known size."""
+    f = float(kv["fetch_kib_per_launch"]) * 1024.0
+    w = float(kv["write_kib_per_launch"]) * 1024.0
+    fc = float(kv["copy_fetch_kib"]) * 1024.0
+    wc = float(kv["copy_write_kib"]) * 1024.0
+    cb = float(kv["copy_bytes"])
+    return f * cb / fc + w * cb / wc
 
 
 def main():
@@ -134,7 +297,17 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--path", default="auto", choices=["auto", "direct"],
                     help="kernel: LDS-pipelined (auto) or direct-load")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with three 1 GiB device copies (counter "
+                         "calibration under rocprofv3 --pmc)")
+    ap.add_argument("--summarize-profile", nargs="+", metavar="DIR",
+                    help="print a text summary of rocprofv3 CSV output "
+                         "directories and exit")
     args = ap.parse_args()
+    if args.summarize_profile:
+        print(summarize_profile(args.summarize_profile,
+                                WORKLOADS[args.workload][6]))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for "
               f"{args.gpus}); the multi-GPU design is documented but not "
@@ -162,7 +335,16 @@ def main():
             "stage_kernel_ms": [round(x, 4) for x in per_stage],
             "achieved_gbs": ach,
         }
+    if args.calibrate_copy:
+        calibrate_copy(torch)
     f = res["f64"]
+    lds = args.path == "auto"
+    kernel = f"k_stage_lds<{order},false>" if lds else f"k_stage<{order},...>"
+    kv, tsrc = (profile_figures(args.workload, f"k_stage_lds_o{order}")
+                if lds else (None, "no counter summary for this kernel"))
+    traffic = traffic_bytes(kv) if kv and "fetch_kib_per_launch" in kv \
+        else None
+    avg_s = sum(f["stage_kernel_ms"]) / 4 * 1e-3
     out = {
         "metric": "BSSN RHS+RK4 grid-point updates/s, FP64 vs mixed, % of "
                   "HBM roofline",
@@ -182,11 +364,24 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(f["achieved_gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(f["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": None,
-                     "kernel": "k_stage (fused RHS + RK4 stage), mean of the "
-                               "4 stage launches weighted by their bytes",
+                     "traffic": (None if traffic is None else
+                                 round(traffic)),
+                     "traffic_unit": "HBM bytes per stage launch (mean of "
+                                     "the 4 stages)",
+                     "traffic_source": tsrc,
+                     "algorithmic_bytes_per_launch":
+                         sum(b * N for b in STAGE_BYTES) / 4,
+                     "kernel": kernel + " (fused RHS + RK4 stage)",
+                     "avg_launch_ms": round(sum(f["stage_kernel_ms"]) / 4, 4),
                      "stage_kernel_ms": f["stage_kernel_ms"]},
     }
+    if kv and "valu_flops_f64_per_launch" in kv:
+        fl = float(kv["valu_flops_f64_per_launch"])
+        out["valu"] = {"flops_f64_per_launch": fl,
+                       "achieved": round(fl / avg_s / 1e12, 2),
+                       "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(fl / avg_s / 1e12 / FP64_PEAK_TFLOPS, 4),
+                       "source": tsrc}
     if "mixed" in res:
         m = res["mixed"]
         out["mixed"] = {"value": m["value"], "ms_per_step": m["ms_per_step"],
