@@ -53,6 +53,10 @@ WORKLOADS = {
            "c3: two Brill-Lindquist punctures m=0.5 at (+-3,0,0), 256^3 + 3 "
            "ghosts on [-16,16]^3, static boundary, 4th-order FD, RK4 "
            "dt=0.03125"),
+    "c4": (None, None, None, 3, None, None, 4, 0.03125,
+           "c4: 256 uneven static patches, interiors U{24..96} per axis, "
+           "3 ghosts, h=0.125, one Brill-Lindquist puncture each (mass "
+           "U[0.3,1.0], seeded centre), 4th order, RK4 dt=0.03125"),
     "c5": (384, -24.0, 24.0, 5, (0.6, 0.4), ((4.0, 0, 0), (-4.0, 0, 0)), 8,
            0.03125,
            "c5: two Brill-Lindquist punctures m=0.6/0.4 at (+-4,0,0), 384^3 "
@@ -287,6 +291,106 @@ def traffic_bytes(kv):
     return f * cb / fc + w * cb / wc
 
 
+def batched(B, torch, steps, warmup, npatch=256):
+    """256 uneven static patches (interiors U{24..96} per axis, h = 0.125,
+    one Brill-Lindquist puncture each): a batch plan (autotuned) advanced
+    with batch_patches (one graph replay per RK4 step) against one launch
+    per patch and stage, FP64 and mixed."""
+    from paper_1111_3344_amd import inputs as I
+    specs = I.patches(npatch)
+    grids = [g for g, _, _ in specs]
+    u = []
+    for g, m, c in specs:  # host copies one at a time
+        u.append(torch.from_numpy(I.brill_lindquist(g, (m,), (c,))).to("cuda"))
+    a = [t.clone() for t in u]
+    b = [t.clone() for t in u]
+    acc = [torch.zeros_like(t) for t in u]
+    N = sum(g.npoints for g in grids)
+    stream = torch.cuda.current_stream()
+    out = {"interior_points": N, "npatch": npatch}
+    for label, prec in (("f64", B.BSSN_FP64), ("mixed", B.BSSN_MIXED)):
+        plan = B.batch_patches_plan(grids, B.Params(precision=prec), u, a, b,
+                                    acc, 0.03125, autotune=True)
+        r = {"classes": [list(c) for c in B.batch_patches_describe(plan)]}
+        for mode, fn in (("batched", B.batch_patches),
+                         ("per_patch", B.batch_patches_unbatched)):
+            fn(plan, warmup, stream)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(stream)
+            fn(plan, steps, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            r[mode] = {"value": N * steps / wall,
+                       "ms_per_step": 1e3 * wall / steps,
+                       "gpu_ms_per_step": e0.elapsed_time(e1) / steps,
+                       "hbm_frac": round(3200.0 * N * steps / wall / 1e9 /
+                                         HBM_PEAK_GBS, 4)}
+        plan.destroy()
+        out[label] = r
+    return out
+
+
+ACCURACY_STEPS = {"c1": 1, "c2": 100, "c3": 200, "c5": 50}
+
+
+def accuracy(B, torch, name, steps=None, r_exc=1.0):
+    """FP64 and mixed-precision runs of a workload for its step count: the
+    mixed run's field error against the FP64 run (per slot, normwise: max
+    and L2 of |mixed - fp64| over max |fp64| of that slot; the FP64 path
+    matches the oracle to 1e-12 per step) and both runs' constraint norms
+    (points closer than r_exc to a puncture left out)."""
+    g, u, order, dt, desc = build_state(name)
+    steps = steps or ACCURACY_STEPS[name]
+    centres = WORKLOADS[name][5] or ()
+    res = {}
+    ref = None
+    for label, prec in (("f64", B.BSSN_FP64), ("mixed", B.BSSN_MIXED)):
+        prm = B.Params(fd_order=order, precision=prec)
+        du = torch.from_numpy(u).to("cuda")
+        a, b, acc = du.clone(), du.clone(), torch.zeros_like(du)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            B.rk4_step(g, prm, dt, du, a, b, acc)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        del a, b, acc
+        norms = torch.zeros(8, dtype=torch.float64, device="cuda")
+        B.bssn_constraints(g, B.Params(fd_order=order), du, norms,
+                           centres=centres, r_exc=r_exc if centres else 0.0)
+        n = norms.cpu().numpy()
+        r = {"H_rms": n[0], "H_max": n[1], "M_rms": n[2], "M_max": n[3],
+             "G_rms": n[4], "points": int(n[6]), "nonfinite": int(n[7]),
+             "seconds": round(wall, 3)}
+        if prec == B.BSSN_MIXED:
+            n64, nt = B.bssn_mixed_tile_count(g, prm, du)
+            r["fp64_tiles"] = f"{n64}/{nt} (final state)"
+        if ref is None:
+            ref = du
+        else:
+            mx, l2 = [], []
+            for sl in range(25):
+                x = g.interior(ref)[sl]
+                y = g.interior(du)[sl]
+                D = float(x.abs().max())
+                D = D if D > 0 else 1.0
+                d = (y - x).abs()
+                mx.append(float(d.max()) / D)
+                l2.append(float(d.pow(2).mean().sqrt()) / D)
+            r["field_err_vs_f64_max"] = max(mx)
+            r["field_err_vs_f64_l2"] = max(l2)
+            r["worst_slot"] = mx.index(max(mx))
+            r["H_rms_ratio"] = r["H_rms"] / res["f64"]["H_rms"]
+            r["M_rms_ratio"] = r["M_rms"] / res["f64"]["M_rms"]
+            del du
+        res[label] = r
+    return {"accuracy": name, "workload": desc, "steps": steps, "dt": dt,
+            "r_exc": r_exc if centres else None, **res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,6 +404,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three 1 GiB device copies (counter "
                          "calibration under rocprofv3 --pmc)")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="FP64 vs mixed runs of the workload for its step "
+                         "count: field errors and constraint norms")
     ap.add_argument("--summarize-profile", nargs="+", metavar="DIR",
                     help="print a text summary of rocprofv3 CSV output "
                          "directories and exit")
@@ -318,6 +425,14 @@ def main():
 
     B.bssn_set_path(B.BSSN_PATH_DIRECT if args.path == "direct"
                     else B.BSSN_PATH_AUTO)
+    if args.workload == "c4":
+        r = batched(B, torch, args.steps, args.warmup)
+        print(json.dumps({"workload": WORKLOADS["c4"][8], "steps": args.steps,
+                          "warmup": args.warmup, **r}), flush=True)
+        return
+    if args.accuracy:
+        print(json.dumps(accuracy(B, torch, args.workload)), flush=True)
+        return
     g, u, order, dt, desc = build_state(args.workload)
     N = g.npoints
     res = {}

@@ -171,8 +171,12 @@ int bssn_constraints(const bssn_grid* grid, const bssn_params* params,
                      double* norms, void* stream);
 
 /* Number of tiles a BSSN_MIXED evaluation of u runs in FP64 (tiles whose
- * minimum lapse is below params->fp64_alpha_threshold) and the total number
- * of tiles.  Synchronous; n_fp64 and n_tiles are host pointers. */
+ * minimum lapse over their points is below params->fp64_alpha_threshold)
+ * and the total number of tiles.  Tiles are those of the kernel a stage on
+ * this grid runs under the current bssn_set_path: 16 x 4 x 4 points for the
+ * LDS-pipelined kernel (static grids), single-plane 64 x 4 (n[0] > 32) or
+ * 32 x 8 for the direct kernel.  Synchronous; n_fp64 and n_tiles are host
+ * pointers. */
 int bssn_mixed_tile_count(const bssn_grid* grid, const bssn_params* params,
                           const double* u, int64_t* n_fp64, int64_t* n_tiles,
                           void* stream);

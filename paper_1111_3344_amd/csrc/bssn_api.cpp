@@ -312,16 +312,20 @@ int bssn_mixed_tile_count(const bssn_grid* grid, const bssn_params* params,
   }
   Patch P = make_patch(grid);
   P.u_s = u;
+  // the tiles of the kernel a stage on this grid runs
+  const int lds = grid->bc == BSSN_BC_STATIC && stage_path() == PATH_AUTO &&
+                  variant_ok(P, params->fd_order, VAR_LDS);
   hipError_t e = hipMemsetAsync(ws->counter, 0, sizeof(unsigned long long), st);
   if (e == hipSuccess)
-    e = launch_tile_count(P, params->fp64_alpha_threshold, ws->counter, st);
+    e = launch_tile_count(P, params->fp64_alpha_threshold, lds, ws->counter,
+                          st);
   unsigned long long h = 0;
   if (e == hipSuccess)
     e = hipMemcpyAsync(&h, ws->counter, sizeof h, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "bssn_mixed_tile_count");
   dim3 grd, blk;
-  tile_grid(P, grd, blk);
+  tile_grid(P, lds, grd, blk);
   *n_fp64 = (int64_t)h;
   *n_tiles = (int64_t)grd.x * grd.y * grd.z;
   g_err = "no error";

@@ -7,10 +7,10 @@
 // a multiple of 16 points), picks one kernel variant per class (timed trial
 // launches, or a default), and builds per variant a device work list over
 // all patches of the classes that chose it:
-//   VAR_LDS  runs of LDS tiles; the tiles of all its patches, in class and
-//            patch order, are split evenly over one persistent workgroup per
-//            compute unit, and each workgroup's share is cut at patch
-//            boundaries into items (patch, first tile, end tile);
+//   VAR_LDS  runs of LDS tiles: one persistent workgroup per compute unit;
+//            whole patches are assigned to XCDs (balanced by tile count) and
+//            each patch's tiles are split evenly over the workgroups of its
+//            XCD, one item (patch, first tile, end tile) per workgroup;
 //   VAR_D*   one item per direct-kernel workgroup (patch, x0, y0, z).
 // The four stages of an RK4 step (one launch per variant in use per stage)
 // are captured once into a hipGraph; batch_patches replays it per step.
@@ -69,37 +69,85 @@ int build_group(const std::vector<bssn_grid>& grids,
   G = HostGroup();
   G.variant = variant;
   if (variant == VAR_LDS) {
-    std::vector<int64_t> start(pids.size() + 1, 0);
+    // XCD-affine: workgroup b runs on XCD b mod 8 and takes the item list
+    // of position q = walk_pos(b), so positions [x*W, (x+1)*W) (W = nwg/8)
+    // are the workgroups of XCD x.  Whole patches go to XCDs by a
+    // longest-processing-time greedy on tile count; each patch's tiles are
+    // split evenly over its XCD's W workgroups, in the single-patch order,
+    // so neighbouring columns run at the same time on one XCD and their
+    // halos meet in its L2, and a workgroup's share of a patch (tiles / W)
+    // is long compared with the drift between workgroups.  Patches smaller
+    // than W tiles start at a rotating offset.  With nwg not a multiple
+    // of 8 the whole GPU acts as one group.
+    std::vector<int64_t> tiles(pids.size());
+    int64_t T = 0;
     for (size_t i = 0; i < pids.size(); ++i) {
       int ntx, nty, ntz;
       lds_tiles_of(grids[pids[i]], ntx, nty, ntz);
-      start[i + 1] = start[i] + int64_t(ntx) * nty * ntz;
+      tiles[i] = int64_t(ntx) * nty * ntz;
+      T += tiles[i];
+      if (tiles[i] >= (int64_t(1) << 31) / 2)
+        return fail(BSSN_EUNSUPPORTED, "batch: a patch of %lld LDS tiles "
+                    "exceeds the work-list range", (long long)tiles[i]);
     }
-    const int64_t T = start.back();
-    if (T >= (int64_t(1) << 31) / 2)
-      return fail(BSSN_EUNSUPPORTED, "batch: %lld LDS tiles exceed the "
-                  "work-list range", (long long)T);
     const int nwg = int(std::min<int64_t>(nwg_max, T));
+    const int ngrp = (nwg % 8 == 0) ? 8 : 1;
+    const int W = nwg / ngrp;
     G.nwg = nwg;
-    G.wstart.assign(nwg + 1, 0);
-    size_t i = 0;  // patch whose tiles contain the current global tile
-    for (int q = 0; q < nwg; ++q) {
-      G.wstart[q] = int32_t(G.lds.size());
-      int64_t lo = T * q / nwg;
-      const int64_t hi = T * (q + 1) / nwg;
-      while (lo < hi) {
-        while (start[i + 1] <= lo) ++i;
-        const int64_t end = std::min(hi, start[i + 1]);
-        const bssn_grid& g = grids[pids[i]];
+    // A patch larger than one group's fair share (T / ngrp) is spread over
+    // every group: group x takes the x-th eighth of its tiles.  Smaller
+    // patches go whole to the least-loaded group, largest first.
+    struct Piece {
+      int i;
+      int64_t lo, hi;
+    };
+    std::vector<std::vector<Piece>> mine(ngrp);
+    std::vector<int64_t> load(ngrp, 0);
+    std::vector<int> order(pids.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = int(i);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return tiles[x] > tiles[y]; });
+    for (int i : order) {
+      if (ngrp > 1 && tiles[i] * ngrp >= T) {
+        for (int x = 0; x < ngrp; ++x) {
+          const Piece pc{i, tiles[i] * x / ngrp, tiles[i] * (x + 1) / ngrp};
+          load[x] += pc.hi - pc.lo;
+          mine[x].push_back(pc);
+        }
+        continue;
+      }
+      const int x = int(std::min_element(load.begin(), load.end()) -
+                        load.begin());
+      load[x] += tiles[i];
+      mine[x].push_back(Piece{i, 0, tiles[i]});
+    }
+    std::vector<std::vector<LdsItem>> per(nwg);
+    for (int x = 0; x < ngrp; ++x) {
+      std::sort(mine[x].begin(), mine[x].end(),
+                [](const Piece& a, const Piece& b) { return a.i < b.i; });
+      int rot = 0;
+      for (const Piece& pc : mine[x]) {
         LdsItem it;
-        it.patch = pids[i];
-        it.tlo = int32_t(lo - start[i]);
-        it.thi = int32_t(end - start[i]);
-        lds_tiles_of(g, it.ntx, it.nty, it.ntz);
-        G.lds.push_back(it);
-        lo = end;
+        it.patch = pids[pc.i];
+        lds_tiles_of(grids[pids[pc.i]], it.ntx, it.nty, it.ntz);
+        const int64_t t = pc.hi - pc.lo;
+        for (int l = 0; l < W; ++l) {
+          const int64_t lo = pc.lo + t * l / W, hi = pc.lo + t * (l + 1) / W;
+          if (hi <= lo) continue;
+          it.tlo = int32_t(lo);
+          it.thi = int32_t(hi);
+          per[x * W + (t < W ? (l + rot) % W : l)].push_back(it);
+        }
+        if (t < W) rot = int((rot + t) % W);
       }
     }
+    G.wstart.assign(nwg + 1, 0);
+    for (int q = 0; q < nwg; ++q) {
+      G.wstart[q] = int32_t(G.lds.size());
+      G.lds.insert(G.lds.end(), per[q].begin(), per[q].end());
+    }
+    if (G.lds.size() >= size_t(1) << 31)
+      return fail(BSSN_EUNSUPPORTED, "batch: work list too long");
     G.wstart[nwg] = int32_t(G.lds.size());
     return BSSN_OK;
   }

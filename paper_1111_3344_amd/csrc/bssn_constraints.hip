@@ -421,17 +421,51 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0 && threadIdx.y == 0 && f64) atomicAdd(counter, 1ull);
 }
 
-void tile_grid(const Patch& P, dim3& grd, dim3& blk) {
+// The same predicate over the LDS kernel's 16 x 4 x 4 tiles (one block per
+// tile, thread = point as in that kernel).
+__global__ void __launch_bounds__(256)
+    k_tile_count_lds(const Patch P, const double thr, const int ntx,
+                     const int nty, unsigned long long* __restrict__ counter) {
+  const int t = blockIdx.x, tid = threadIdx.x;
+  const int ix = t % ntx, iy = (t / ntx) % nty, iz = t / (ntx * nty);
+  const int x = ix * kLdsTile[0] + (tid & 15);
+  const int y = iy * kLdsTile[1] + ((tid >> 4) & 3);
+  const int z = iz * kLdsTile[2] + (tid >> 6);
+  const bool active = x < P.n[0] && y < P.n[1] && z < P.n[2];
+  const int g = P.ghost;
+  const uint32_t vc = uint32_t(z + g) * uint32_t(P.sz) * 8u +
+                      uint32_t(y + g) * uint32_t(P.sy) * 8u +
+                      uint32_t(x + g) * 8u;
+  const bool f64 = tile_needs_fp64(P, active, vc, int32_t(P.sf * 8), thr);
+  if (tid == 0 && f64) atomicAdd(counter, 1ull);
+}
+
+void tile_grid(const Patch& P, int lds, dim3& grd, dim3& blk) {
+  if (lds) {
+    const int ntx = (P.n[0] + kLdsTile[0] - 1) / kLdsTile[0];
+    const int nty = (P.n[1] + kLdsTile[1] - 1) / kLdsTile[1];
+    const int ntz = (P.n[2] + kLdsTile[2] - 1) / kLdsTile[2];
+    grd = dim3(ntx * nty * ntz, 1, 1);
+    blk = dim3(256, 1, 1);
+    return;
+  }
   stage_tile_shape(P, 0, blk);
   grd = dim3((P.n[0] + blk.x - 1) / blk.x, (P.n[1] + blk.y - 1) / blk.y,
              P.n[2]);
 }
 
-hipError_t launch_tile_count(const Patch& P, double thr,
+hipError_t launch_tile_count(const Patch& P, double thr, int lds,
                              unsigned long long* counter, hipStream_t st) {
   dim3 grd, blk;
-  tile_grid(P, grd, blk);
-  hipLaunchKernelGGL(k_tile_count, grd, blk, 0, st, P, thr, counter);
+  tile_grid(P, lds, grd, blk);
+  if (lds) {
+    const int ntx = (P.n[0] + kLdsTile[0] - 1) / kLdsTile[0];
+    const int nty = (P.n[1] + kLdsTile[1] - 1) / kLdsTile[1];
+    hipLaunchKernelGGL(k_tile_count_lds, grd, blk, 0, st, P, thr, ntx, nty,
+                       counter);
+  } else {
+    hipLaunchKernelGGL(k_tile_count, grd, blk, 0, st, P, thr, counter);
+  }
   return hipGetLastError();
 }
 

@@ -95,9 +95,10 @@ hipError_t launch_constraints(const ConstraintArgs& A, int order,
                               double* norms, hipStream_t st);
 int constraint_blocks(const ConstraintArgs& A);
 
-// Count of tiles whose minimum lapse is below thr (device counter).
-hipError_t launch_tile_count(const Patch& P, double thr,
+// Count of tiles whose minimum lapse is below thr (device counter), over
+// the tiles of the LDS kernel (lds = 1) or of the direct kernel.
+hipError_t launch_tile_count(const Patch& P, double thr, int lds,
                              unsigned long long* counter, hipStream_t st);
-void tile_grid(const Patch& P, dim3& grd, dim3& blk);
+void tile_grid(const Patch& P, int lds, dim3& grd, dim3& blk);
 
 }  // namespace bssn
