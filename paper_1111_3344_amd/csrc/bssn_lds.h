@@ -268,6 +268,7 @@ struct LdLds {
 // x/y halos meet in that XCD's L2.
 struct TileMap {
   int ntx, nty, ntz, ntiles;
+  int bx, by, bz;  // block shape of the blocked walk, bx = 0: contiguous
 };
 __host__ __device__ __forceinline__ int walk_pos(int wg, int nwg) {
   return (nwg & 7) == 0 ? (wg & 7) * (nwg >> 3) + (wg >> 3) : wg;
@@ -279,37 +280,64 @@ __host__ __device__ __forceinline__ void walk_range(int lin, int nwg,
   hi = int((int64_t(ntiles) * (lin + 1)) / nwg);
 }
 
+// The tiles one workgroup visits, in order.  Contiguous: tiles
+// [tlo, tlo + n) of the TileMap numbering.  Blocked (single patches whose
+// tile grid divides into blocks): the 32 workgroups of one XCD work on one
+// block of bx x by x bz tiles at a time, one tile each, and step through
+// the block's column together in z by bz tiles, then move on to the XCD's
+// next block column.  Neighbouring tiles in x, y and z are then fetched at
+// the same time on one XCD, and between two z-steps the L2 only has to keep
+// the overlap planes of a (16 bx + 2R) x (4 by + 2R) footprint.
+struct WalkContig {
+  int tlo, n, ntx, ntz;
+  __device__ __forceinline__ int count() const { return n; }
+  __device__ __forceinline__ void origin(int k, int& x0, int& y0,
+                                         int& z0) const {
+    const int t = tlo + k;
+    const int iz = t % ntz, col = t / ntz;
+    x0 = (col % ntx) * kLdsTile[0];
+    y0 = (col / ntx) * kLdsTile[1];
+    z0 = iz * kLdsTile[2];
+  }
+};
+struct WalkBlocked {
+  int lx, ly, lz;      // this workgroup's tile within a block
+  int bx, by, bz;      // block shape in tiles (bx * by * bz = 32)
+  int xcd, nrx, nk;    // XCD, blocks along x, z-steps per block column
+  int n;               // tiles this workgroup visits
+  __device__ __forceinline__ int count() const { return n; }
+  __device__ __forceinline__ void origin(int k, int& x0, int& y0,
+                                         int& z0) const {
+    const int r = xcd + 8 * (k / nk), kz = k % nk;
+    x0 = ((r % nrx) * bx + lx) * kLdsTile[0];
+    y0 = ((r / nrx) * by + ly) * kLdsTile[1];
+    z0 = (kz * bz + lz) * kLdsTile[2];
+  }
+};
+
 // Tiles [tlo, thi) of patch P (numbered as in TileMap), pipelined through
 // the workgroup's LDS ring.  MIXED = false: FP64 everywhere.  MIXED = true:
 // per tile, FP32 stencils and algebra unless the tile's minimum lapse is
 // below G.alpha_thr (then FP64); the branch is uniform over the workgroup.
 // On return every DMA of this call has landed; the caller places a barrier
 // before the ring is filled again.
-template <int ORDER, bool MIXED>
+template <int ORDER, bool MIXED, class Walk>
 __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
-                                          const int stage, const TileMap& M,
-                                          const int tlo, const int thi,
+                                          const int stage, const Walk& Wk,
                                           double* ring, double* sc) {
   using Geo = TileGeo<ORDER>;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int tx = lane & 15, ty = lane >> 4, tz = wave;
-  const int ntile_mine = thi - tlo;
+  const int ntile_mine = Wk.count();
   if (ntile_mine <= 0) return;
-
-  auto origin = [&](int t, int& x0, int& y0, int& z0) {
-    const int iz = t % M.ntz, col = t / M.ntz;
-    x0 = (col % M.ntx) * Geo::TX;
-    y0 = (col / M.ntx) * Geo::TY;
-    z0 = iz * Geo::TZ;
-  };
   uint32_t offA[Geo::L], offB[Geo::L];
   int x0, y0, z0, xn, yn, zn;
   {
-    origin(tlo, x0, y0, z0);
+    Wk.origin(0, x0, y0, z0);
     dma_offsets<Geo>(P, x0, y0, z0, wave, lane, offA);
-    origin(ntile_mine > 1 ? tlo + 1 : tlo, xn, yn, zn);
+    Wk.origin(ntile_mine > 1 ? 1 : 0, xn, yn, zn);
     dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
   }
   // prologue: centre block and phases 0 .. NBUF-2 of the first tile
@@ -321,7 +349,7 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
   const int32_t nbytes = int32_t(P.sf * 8);
   const uint32_t sy8 = uint32_t(P.sy) * 8u, sz8 = uint32_t(P.sz) * 8u;
   for (int k = 0; k < ntile_mine; ++k) {
-    origin(tlo + k, x0, y0, z0);
+    Wk.origin(k, x0, y0, z0);
     const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
     const bool active = x < P.n[0] && y < P.n[1] && z < P.n[2];
     const int g = P.ghost;
@@ -373,7 +401,7 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
 #pragma unroll
     for (int j = 0; j < Geo::L; ++j) offA[j] = offB[j];
     if (k + 2 < ntile_mine) {
-      origin(tlo + k + 2, xn, yn, zn);
+      Wk.origin(k + 2, xn, yn, zn);
       dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
     }
   }
@@ -391,9 +419,27 @@ __global__ void __launch_bounds__(256)
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
   const int nwg = gridDim.x;
-  int tlo, thi;
-  walk_range(walk_pos(blockIdx.x, nwg), nwg, M.ntiles, tlo, thi);
-  lds_tiles<ORDER, MIXED>(P, G, stage, M, tlo, thi, ring, sc);
+  if (M.bx > 0) {
+    WalkBlocked w;
+    w.xcd = blockIdx.x & 7;
+    const int l = blockIdx.x >> 3;
+    w.lx = l % M.bx;
+    w.ly = (l / M.bx) % M.by;
+    w.lz = l / (M.bx * M.by);
+    w.bx = M.bx;
+    w.by = M.by;
+    w.bz = M.bz;
+    w.nrx = M.ntx / M.bx;
+    w.nk = M.ntz / M.bz;
+    const int nblk = w.nrx * (M.nty / M.by);
+    w.n = (nblk > w.xcd ? (nblk - w.xcd + 7) / 8 : 0) * w.nk;
+    lds_tiles<ORDER, MIXED>(P, G, stage, w, ring, sc);
+  } else {
+    int tlo, thi;
+    walk_range(walk_pos(blockIdx.x, nwg), nwg, M.ntiles, tlo, thi);
+    WalkContig w{tlo, thi - tlo, M.ntx, M.ntz};
+    lds_tiles<ORDER, MIXED>(P, G, stage, w, ring, sc);
+  }
 }
 
 // Many patches: workgroup b runs the items [wstart[q], wstart[q+1]) for
@@ -412,12 +458,8 @@ __global__ void __launch_bounds__(256)
   for (int i = i0; i < i1; ++i) {
     const LdsItem it = items[i];
     const Patch P = patches[it.patch];
-    TileMap M;
-    M.ntx = it.ntx;
-    M.nty = it.nty;
-    M.ntz = it.ntz;
-    M.ntiles = it.ntx * it.nty * it.ntz;
-    lds_tiles<ORDER, MIXED>(P, G, stage, M, it.tlo, it.thi, ring, sc);
+    WalkContig w{it.tlo, it.thi - it.tlo, it.ntx, it.ntz};
+    lds_tiles<ORDER, MIXED>(P, G, stage, w, ring, sc);
     __builtin_amdgcn_s_barrier();  // every wave is done with ring and sc
   }
 }
@@ -430,7 +472,26 @@ inline TileMap lds_tile_map(const Patch& P) {
   M.nty = (P.n[1] + Geo::TY - 1) / Geo::TY;
   M.ntz = (P.n[2] + Geo::TZ - 1) / Geo::TZ;
   M.ntiles = M.ntx * M.nty * M.ntz;
+  M.bx = M.by = M.bz = 0;
   return M;
+}
+
+// Blocked walk (WalkBlocked) for a launch of 256 workgroups: the first
+// block shape of 32 tiles that divides the tile grid and leaves every XCD
+// at least one block; otherwise the contiguous walk.
+inline void choose_blocks(TileMap& M, int nwg) {
+  static const int shapes[][3] = {{4, 4, 2}, {2, 4, 4}, {4, 2, 4},
+                                  {2, 2, 8}, {4, 8, 1}, {8, 4, 1}};
+  M.bx = M.by = M.bz = 0;
+  if (nwg != 256) return;
+  for (const auto& b : shapes) {
+    if (M.ntx % b[0] || M.nty % b[1] || M.ntz % b[2]) continue;
+    if ((M.ntx / b[0]) * (M.nty / b[1]) < 8) continue;
+    M.bx = b[0];
+    M.by = b[1];
+    M.bz = b[2];
+    return;
+  }
 }
 
 // The LDS path needs 16-byte aligned granules: (u + ghost - R - 1) aligned
@@ -451,8 +512,9 @@ namespace bssn {
 template <int ORDER>
 hipError_t launch_stage_lds(const Patch& P, const Gauge& G, int stage,
                             int precision, int nwg_max, hipStream_t st) {
-  const TileMap M = lds_tile_map<ORDER>(P);
+  TileMap M = lds_tile_map<ORDER>(P);
   const int nwg = M.ntiles < nwg_max ? M.ntiles : nwg_max;
+  choose_blocks(M, nwg);
   if (precision == 0)
     hipLaunchKernelGGL((k_stage_lds<ORDER, false>), dim3(nwg), dim3(256), 0,
                        st, P, G, stage, M);

@@ -33,6 +33,19 @@ __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r,
   return __builtin_bit_cast(double, v);
 }
 
+__device__ __forceinline__ double bload_nt(__amdgpu_buffer_rsrc_t r,
+                                        uint32_t voff) {
+  auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, 0, 2);
+  return __builtin_bit_cast(double, v);
+}
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                       double x) {
+  __builtin_amdgcn_raw_buffer_store_b64(
+      __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(
+                             r, 0, 0, 0)),
+                         x),
+      r, (int)voff, 0, 2);
+}
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                        double x) {
   __builtin_amdgcn_raw_buffer_store_b64(
@@ -130,40 +143,40 @@ __device__ __forceinline__ void epilogue(const Patch& P, int stage,
   if (stage == ST_RHS) {
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s)
-      bstore(rsrc(P.out + s * P.sf, nbytes), vc, double(r[s]));
+      bstore_nt(rsrc(P.out + s * P.sf, nbytes), vc, double(r[s]));
     return;
   }
   double un[NSLOT], ac[NSLOT];
   if (stage != ST_3) {
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s)
-      un[s] = bload(rsrc(P.u_n + s * P.sf, nbytes), vc, 0);
+      un[s] = bload_nt(rsrc(P.u_n + s * P.sf, nbytes), vc);
   }
   if (stage != ST_0) {
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s)
-      ac[s] = bload(rsrc(P.acc + s * P.sf, nbytes), vc, 0);
+      ac[s] = bload_nt(rsrc(P.acc + s * P.sf, nbytes), vc);
   }
   BSSN_PHASE();  // loads above, stores below
   if (stage == ST_3) {
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s)
-      bstore(rsrc(P.out + s * P.sf, nbytes), vc,
+      bstore_nt(rsrc(P.out + s * P.sf, nbytes), vc,
              ac[s] + (dt / 6.0) * double(r[s]));
   } else if (stage == ST_0) {
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
       const double k = double(r[s]);
-      bstore(rsrc(P.acc + s * P.sf, nbytes), vc, un[s] + (dt / 6.0) * k);
-      bstore(rsrc(P.out + s * P.sf, nbytes), vc, un[s] + (dt / 2.0) * k);
+      bstore_nt(rsrc(P.acc + s * P.sf, nbytes), vc, un[s] + (dt / 6.0) * k);
+      bstore_nt(rsrc(P.out + s * P.sf, nbytes), vc, un[s] + (dt / 2.0) * k);
     }
   } else {
     const double c = stage == ST_1 ? dt / 2.0 : dt;
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
       const double k = double(r[s]);
-      bstore(rsrc(P.acc + s * P.sf, nbytes), vc, ac[s] + (dt / 3.0) * k);
-      bstore(rsrc(P.out + s * P.sf, nbytes), vc, un[s] + c * k);
+      bstore_nt(rsrc(P.acc + s * P.sf, nbytes), vc, ac[s] + (dt / 3.0) * k);
+      bstore_nt(rsrc(P.out + s * P.sf, nbytes), vc, un[s] + c * k);
     }
   }
 }
