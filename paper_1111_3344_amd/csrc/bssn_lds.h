@@ -39,7 +39,9 @@ struct TileGeo<4> {
   static constexpr int H = TY + 2 * R, D = TZ + 2 * R;
   static constexpr int G = W * H * D / 2;    // granules per box
   static constexpr int L = (G + 255) / 256;  // DMA instructions per wave
-  static constexpr int NBUF = 6;             // ring of boxes in LDS
+  static constexpr int NBUF = 5;             // ring of boxes in LDS; it
+                                             // divides NSLOT, so every
+                                             // phase's buffer is static
   static constexpr int BUFD = L * 256 * 2;   // doubles per buffer
 };
 template <>
@@ -87,17 +89,6 @@ __device__ __forceinline__ void dma_offsets(const Patch& P, int x0, int y0,
                       (x0 + g - Geo::R - 1) + 2 * col;
     off[j] = uint32_t(e * 8);  // < 0 wraps to a huge offset: reads 0
   }
-}
-
-// Buffer resource of slot s built where it is used: the base goes through an
-// opaque scalar move so the 25 per-slot descriptors are not all hoisted out
-// of the tile loop (that would pin ~100 SGPRs).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t slot_rsrc(const double* u,
-                                                            int64_t sf, int s,
-                                                            int32_t nbytes) {
-  const double* b = u;
-  asm volatile("" : "+s"(b));  // opaque here, so b + s*sf stays here too
-  return rsrc(b + s * sf, nbytes);
 }
 
 // One buffer->LDS DMA instruction: every lane moves the 16 bytes at
@@ -185,6 +176,29 @@ __device__ __forceinline__ void centre_dma(const Patch& P, double* sc,
   }
 }
 
+// s_waitcnt vmcnt(min(N + extra, 63)) lgkmcnt(0) for extra a multiple of
+// NSLOT (0 .. 4 NSLOT), rounded down to a value that is never above the
+// true count.
+template <int N>
+__device__ __forceinline__ void vm_wait_n() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(N < 63 ? N : 63)
+               : "memory");
+}
+template <int N>
+__device__ __forceinline__ void vm_wait_extra(int extra) {
+  if (extra <= 0)
+    vm_wait_n<N>();
+  else if (extra < 2 * NSLOT)
+    vm_wait_n<N + NSLOT>();
+  else
+    vm_wait_n<N + 2 * NSLOT>();
+}
+
+// The slot whose phase issues the epilogue loads early: the first of the
+// last three phases (the shift), after which only their stencils and a
+// short stretch of algebra remain.
+constexpr int kEpiSlot = BETX;
+
 // Loader used by point_rhs inside the pipelined kernel.  Phase p of the
 // k-th tile of a workgroup is global phase k*NSLOT + p and uses ring buffer
 // (k*NSLOT + p) mod NBUF.
@@ -199,6 +213,16 @@ struct LdLds {
   int pbase;               // (k * NSLOT) mod NBUF
   int wave, lane, tid;
   int cidx;                // element index of the thread's centre in a box
+  // early epilogue loads: issued when the phase of kEpiSlot starts (the
+  // algebra left after it gives their latency something to hide behind)
+  int stage;
+  uint32_t vc_epi;         // byte offset of the point, or out of range
+  int32_t nbytes;
+  int epi_loads;           // loads issued this way at this tile (per wave)
+  int prev_loads;          // the same for the previous tile (0 at the first)
+  int prev_stores;         // stores of the previous tile's epilogue in this
+                           // wave (0 at the first tile)
+  mutable double un[NSLOT], ac[NSLOT];
   // this thread's centre in the current phase's buffer; set per phase
   // through an opaque move so the compiler derives every tap from this one
   // register with immediate offsets instead of hoisting (and spilling) a
@@ -214,24 +238,34 @@ struct LdLds {
   __device__ __forceinline__ void enter(int s) const {
     const int p = phase_of(s);
     if (p != 0) phase(p);  // the kernel runs phase 0 itself
+    if (s == kEpiSlot) epilogue_load(*P, stage, vc_epi, nbytes, un, ac);
     const lds_double* b = (const lds_double*)buffer(p) + cidx;
     asm volatile("" : "+v"(b));
     pc = b;
   }
   // one pipeline step at phase p (0 <= p < NSLOT)
   __device__ __forceinline__ void phase(int p) const {
-    // Wait until this wave's DMA for phase p has landed: newer than it are
-    // the prefetches of phases p+1 .. p+NBUF-2 and, for phases 2 .. NBUF,
-    // the centre block issued at phase 1.  lgkmcnt(0): this wave's reads of
-    // the buffer about to be refilled have completed.
+    // Wait until this wave's DMA for phase p has landed.  vmcnt counts
+    // this wave's memory instructions in issue order, so the count to wait
+    // for is the number issued after that DMA: the prefetches of phases
+    // p+1 .. p+NBUF-2; for phases 2 .. NBUF the centre block issued at
+    // phase 1; after the phase of kEpiSlot, the early epilogue loads; and
+    // at phases 0 .. NBUF-2 of every tile but the first, the previous
+    // tile's epilogue stores, plus its early loads where they followed the
+    // DMA (issued at phase NSLOT + p - NBUF + 1 of that tile).  The field
+    // holds at most 63, and waiting for fewer than that number is always
+    // correct.  lgkmcnt(0): this wave's reads of the buffer about to be
+    // refilled have completed.
+    constexpr int PE = phase_of(kEpiSlot);
+    int extra = 0;
+    if (p > PE) extra = epi_loads;
+    if (p <= Geo::NBUF - 2)
+      extra = prev_stores +
+              (p <= PE - NSLOT + Geo::NBUF - 1 ? prev_loads : 0);
     if (p > kCentrePhase && p <= kCentrePhase + Geo::NBUF - 1)
-      asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(
-                       (Geo::NBUF - 2) * Geo::L + kCentreL)
-                   : "memory");
+      vm_wait_extra<(Geo::NBUF - 2) * Geo::L + kCentreL>(extra);
     else
-      asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(
-                       (Geo::NBUF - 2) * Geo::L)
-                   : "memory");
+      vm_wait_extra<(Geo::NBUF - 2) * Geo::L>(extra);
     __builtin_amdgcn_s_barrier();
     const int q = p + Geo::NBUF - 1;  // phase to prefetch
     uint32_t o[Geo::L];
@@ -280,40 +314,50 @@ __host__ __device__ __forceinline__ void walk_range(int lin, int nwg,
   hi = int((int64_t(ntiles) * (lin + 1)) / nwg);
 }
 
-// The tiles one workgroup visits, in order.  Contiguous: tiles
-// [tlo, tlo + n) of the TileMap numbering.  Blocked (single patches whose
-// tile grid divides into blocks): the 32 workgroups of one XCD work on one
-// block of bx x by x bz tiles at a time, one tile each, and step through
-// the block's column together in z by bz tiles, then move on to the XCD's
-// next block column.  Neighbouring tiles in x, y and z are then fetched at
-// the same time on one XCD, and between two z-steps the L2 only has to keep
-// the overlap planes of a (16 bx + 2R) x (4 by + 2R) footprint.
-struct WalkContig {
-  int tlo, n, ntx, ntz;
+// The tiles one workgroup visits, in order (one walker type, so the
+// right-hand side is inlined once).  Tile k is c = k / nk, kz = k mod nk:
+//   contiguous walk (bx = 0): tiles tlo + k of the TileMap numbering
+//     (z fastest within an (x, y) column); nk = count, c = 0;
+//   blocked walk (single patches whose tile grid divides into blocks of
+//     bx x by x bz = 32 tiles): the 32 workgroups of one XCD hold one tile
+//     each of a block, step through the block's column together in z by
+//     bz tiles, then move on to the XCD's next block (blocks c*8 + xcd).
+//     Neighbouring tiles in x, y and z are then fetched at the same time on
+//     one XCD, and between two z-steps the L2 only has to keep the overlap
+//     planes of a (16 bx + 2R) x (4 by + 2R) footprint.
+struct Walk {
+  int n;            // tiles this workgroup visits
+  int tlo, ntx, ntz;
+  int lx, ly, lz;   // this workgroup's tile within a block
+  int bx, by, bz;   // block shape in tiles (0: contiguous walk)
+  int xcd, nrx, nk;
   __device__ __forceinline__ int count() const { return n; }
   __device__ __forceinline__ void origin(int k, int& x0, int& y0,
                                          int& z0) const {
-    const int t = tlo + k;
-    const int iz = t % ntz, col = t / ntz;
-    x0 = (col % ntx) * kLdsTile[0];
-    y0 = (col / ntx) * kLdsTile[1];
-    z0 = iz * kLdsTile[2];
+    if (bx == 0) {
+      const int t = tlo + k;
+      const int iz = t % ntz, col = t / ntz;
+      x0 = (col % ntx) * kLdsTile[0];
+      y0 = (col / ntx) * kLdsTile[1];
+      z0 = iz * kLdsTile[2];
+    } else {
+      const int r = xcd + 8 * (k / nk), kz = k % nk;
+      x0 = ((r % nrx) * bx + lx) * kLdsTile[0];
+      y0 = ((r / nrx) * by + ly) * kLdsTile[1];
+      z0 = (kz * bz + lz) * kLdsTile[2];
+    }
   }
 };
-struct WalkBlocked {
-  int lx, ly, lz;      // this workgroup's tile within a block
-  int bx, by, bz;      // block shape in tiles (bx * by * bz = 32)
-  int xcd, nrx, nk;    // XCD, blocks along x, z-steps per block column
-  int n;               // tiles this workgroup visits
-  __device__ __forceinline__ int count() const { return n; }
-  __device__ __forceinline__ void origin(int k, int& x0, int& y0,
-                                         int& z0) const {
-    const int r = xcd + 8 * (k / nk), kz = k % nk;
-    x0 = ((r % nrx) * bx + lx) * kLdsTile[0];
-    y0 = ((r / nrx) * by + ly) * kLdsTile[1];
-    z0 = (kz * bz + lz) * kLdsTile[2];
-  }
-};
+__device__ __forceinline__ Walk walk_contig(int tlo, int n, int ntx,
+                                            int ntz) {
+  Walk w{};
+  w.n = n;
+  w.tlo = tlo;
+  w.ntx = ntx;
+  w.ntz = ntz;
+  w.bx = 0;
+  return w;
+}
 
 // Tiles [tlo, thi) of patch P (numbered as in TileMap), pipelined through
 // the workgroup's LDS ring.  MIXED = false: FP64 everywhere.  MIXED = true:
@@ -321,7 +365,7 @@ struct WalkBlocked {
 // below G.alpha_thr (then FP64); the branch is uniform over the workgroup.
 // On return every DMA of this call has landed; the caller places a barrier
 // before the ring is filled again.
-template <int ORDER, bool MIXED, class Walk>
+template <int ORDER, bool MIXED>
 __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
                                           const int stage, const Walk& Wk,
                                           double* ring, double* sc) {
@@ -348,6 +392,7 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
 
   const int32_t nbytes = int32_t(P.sf * 8);
   const uint32_t sy8 = uint32_t(P.sy) * 8u, sz8 = uint32_t(P.sz) * 8u;
+  int prev_loads = 0, prev_stores = 0;  // this wave's last epilogue
   for (int k = 0; k < ntile_mine; ++k) {
     Wk.origin(k, x0, y0, z0);
     const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
@@ -362,15 +407,22 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     ld.nxt[0] = xn;
     ld.nxt[1] = yn;
     ld.nxt[2] = zn;
-    ld.pbase = (k * NSLOT) % Geo::NBUF;
+    ld.pbase = NSLOT % Geo::NBUF == 0 ? 0 : (k * NSLOT) % Geo::NBUF;
     ld.wave = wave;
     ld.lane = lane;
     ld.tid = tid;
+    ld.stage = stage;
+    ld.nbytes = nbytes;
+    ld.epi_loads = epilogue_loads(stage);
+    ld.prev_loads = prev_loads;
+    ld.prev_stores = prev_stores;
     ld.cidx = ((tz + Geo::R) * Geo::H + (ty + Geo::R)) * Geo::W + tx +
               Geo::R + 1;
     const uint32_t vc = active ? uint32_t(z + g) * sz8 + uint32_t(y + g) * sy8 +
                                      uint32_t(x + g) * 8u
                                : 0u;
+    // inactive lanes load from beyond the buffer: no traffic, value 0
+    ld.vc_epi = active ? vc : 0xFFFFFFF0u;
     ld.phase(0);  // phase 0's box and this tile's centre block have landed
     const double xc = P.origin[0] + x * P.h[0];
     const double yc = P.origin[1] + y * P.h[1];
@@ -391,12 +443,16 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     if (f64) {
       double r[NSLOT];
       point_rhs<ORDER, double>(ld, P, xc, yc, zc, G, r);
-      if (active) epilogue<double>(P, stage, r, vc, nbytes);
+      if (active) epilogue_store<double>(P, stage, r, vc, nbytes, ld.un, ld.ac);
     } else {
       float r[NSLOT];
       point_rhs<ORDER, float>(ld, P, xc, yc, zc, G, r);
-      if (active) epilogue<float>(P, stage, r, vc, nbytes);
+      if (active) epilogue_store<float>(P, stage, r, vc, nbytes, ld.un, ld.ac);
     }
+    prev_loads = ld.epi_loads;
+    prev_stores = __builtin_amdgcn_ballot_w64(active) != 0
+                      ? epilogue_stores(stage)
+                      : 0;
     // next tile: its offsets become current, prepare the one after
 #pragma unroll
     for (int j = 0; j < Geo::L; ++j) offA[j] = offB[j];
@@ -419,8 +475,9 @@ __global__ void __launch_bounds__(256)
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
   const int nwg = gridDim.x;
+  Walk w;
   if (M.bx > 0) {
-    WalkBlocked w;
+    w = Walk{};
     w.xcd = blockIdx.x & 7;
     const int l = blockIdx.x >> 3;
     w.lx = l % M.bx;
@@ -433,13 +490,12 @@ __global__ void __launch_bounds__(256)
     w.nk = M.ntz / M.bz;
     const int nblk = w.nrx * (M.nty / M.by);
     w.n = (nblk > w.xcd ? (nblk - w.xcd + 7) / 8 : 0) * w.nk;
-    lds_tiles<ORDER, MIXED>(P, G, stage, w, ring, sc);
   } else {
     int tlo, thi;
     walk_range(walk_pos(blockIdx.x, nwg), nwg, M.ntiles, tlo, thi);
-    WalkContig w{tlo, thi - tlo, M.ntx, M.ntz};
-    lds_tiles<ORDER, MIXED>(P, G, stage, w, ring, sc);
+    w = walk_contig(tlo, thi - tlo, M.ntx, M.ntz);
   }
+  lds_tiles<ORDER, MIXED>(P, G, stage, w, ring, sc);
 }
 
 // Many patches: workgroup b runs the items [wstart[q], wstart[q+1]) for
@@ -458,7 +514,7 @@ __global__ void __launch_bounds__(256)
   for (int i = i0; i < i1; ++i) {
     const LdsItem it = items[i];
     const Patch P = patches[it.patch];
-    WalkContig w{it.tlo, it.thi - it.tlo, it.ntx, it.ntz};
+    const Walk w = walk_contig(it.tlo, it.thi - it.tlo, it.ntx, it.ntz);
     lds_tiles<ORDER, MIXED>(P, G, stage, w, ring, sc);
     __builtin_amdgcn_s_barrier();  // every wave is done with ring and sc
   }
@@ -476,7 +532,7 @@ inline TileMap lds_tile_map(const Patch& P) {
   return M;
 }
 
-// Blocked walk (WalkBlocked) for a launch of 256 workgroups: the first
+// Blocked walk (Walk with bx > 0) for a launch of 256 workgroups: the first
 // block shape of 32 tiles that divides the tile grid and leaves every XCD
 // at least one block; otherwise the contiguous walk.
 inline void choose_blocks(TileMap& M, int nwg) {

@@ -27,6 +27,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const double* base,
                                            kRsrcWord3);
 }
 
+// Buffer resource of slot s built where it is used: the base goes through an
+// opaque scalar move, so the per-slot descriptors of a loop body are not
+// hoisted out of the loop (25 slots x 3 buffers x 4 SGPRs would be spilled
+// to VGPR lanes and moved back on every use).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slot_rsrc(const double* u,
+                                                            int64_t sf, int s,
+                                                            int32_t nbytes) {
+  const double* b = u;
+  asm volatile("" : "+s"(b));  // opaque here, so b + s*sf stays here too
+  return rsrc(b + s * sf, nbytes);
+}
+
 __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r,
                                         uint32_t voff, uint32_t soff) {
   auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
@@ -132,53 +144,82 @@ __device__ __forceinline__ bool tile_needs_fp64(const Patch& P, bool active,
   return m < thr;
 }
 
-// Stage epilogue: k -> acc / out (FP64).  Every load is issued before the
-// first store (the compiler cannot prove the stores of one slot miss the
-// loads of the next, so interleaving them would serialise 25 round trips).
+// Stage epilogue: k -> acc / out (FP64), in two halves so a caller can
+// issue the loads early.  epilogue_load reads u_n (stages 0..2) and acc
+// (stages 1..3) at byte offset vc of every slot; epilogue_store writes acc
+// and the stage output.  Every load is issued before the first store (the
+// compiler cannot prove the stores of one slot miss the loads of the next,
+// so interleaving them would serialise 25 round trips).
+__device__ __forceinline__ void epilogue_load(const Patch& P, int stage,
+                                              uint32_t vc, int32_t nbytes,
+                                              double (&un)[NSLOT],
+                                              double (&ac)[NSLOT]) {
+  if (stage != ST_3 && stage != ST_RHS) {
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s)
+      un[s] = bload_nt(slot_rsrc(P.u_n, P.sf, s, nbytes), vc);
+  }
+  if (stage != ST_0 && stage != ST_RHS) {
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s)
+      ac[s] = bload_nt(slot_rsrc(P.acc, P.sf, s, nbytes), vc);
+  }
+}
+// Memory instructions of the two halves for one wave.
+__device__ __forceinline__ int epilogue_loads(int stage) {
+  return stage == ST_RHS ? 0
+         : (stage == ST_0 || stage == ST_3) ? NSLOT
+                                             : 2 * NSLOT;
+}
+__device__ __forceinline__ int epilogue_stores(int stage) {
+  return (stage == ST_RHS || stage == ST_3) ? NSLOT : 2 * NSLOT;
+}
+
 template <typename T>
-__device__ __forceinline__ void epilogue(const Patch& P, int stage,
-                                         const T (&r)[NSLOT], uint32_t vc,
-                                         int32_t nbytes) {
+__device__ __forceinline__ void epilogue_store(const Patch& P, int stage,
+                                               const T (&r)[NSLOT],
+                                               uint32_t vc, int32_t nbytes,
+                                               const double (&un)[NSLOT],
+                                               const double (&ac)[NSLOT]) {
   const double dt = P.dt;
   if (stage == ST_RHS) {
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s)
-      bstore_nt(rsrc(P.out + s * P.sf, nbytes), vc, double(r[s]));
-    return;
-  }
-  double un[NSLOT], ac[NSLOT];
-  if (stage != ST_3) {
+      bstore_nt(slot_rsrc(P.out, P.sf, s, nbytes), vc, double(r[s]));
+  } else if (stage == ST_3) {
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s)
-      un[s] = bload_nt(rsrc(P.u_n + s * P.sf, nbytes), vc);
-  }
-  if (stage != ST_0) {
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s)
-      ac[s] = bload_nt(rsrc(P.acc + s * P.sf, nbytes), vc);
-  }
-  BSSN_PHASE();  // loads above, stores below
-  if (stage == ST_3) {
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s)
-      bstore_nt(rsrc(P.out + s * P.sf, nbytes), vc,
-             ac[s] + (dt / 6.0) * double(r[s]));
+      bstore_nt(slot_rsrc(P.out, P.sf, s, nbytes), vc,
+                ac[s] + (dt / 6.0) * double(r[s]));
   } else if (stage == ST_0) {
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
       const double k = double(r[s]);
-      bstore_nt(rsrc(P.acc + s * P.sf, nbytes), vc, un[s] + (dt / 6.0) * k);
-      bstore_nt(rsrc(P.out + s * P.sf, nbytes), vc, un[s] + (dt / 2.0) * k);
+      bstore_nt(slot_rsrc(P.acc, P.sf, s, nbytes), vc,
+                un[s] + (dt / 6.0) * k);
+      bstore_nt(slot_rsrc(P.out, P.sf, s, nbytes), vc,
+                un[s] + (dt / 2.0) * k);
     }
   } else {
     const double c = stage == ST_1 ? dt / 2.0 : dt;
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
       const double k = double(r[s]);
-      bstore_nt(rsrc(P.acc + s * P.sf, nbytes), vc, ac[s] + (dt / 3.0) * k);
-      bstore_nt(rsrc(P.out + s * P.sf, nbytes), vc, un[s] + c * k);
+      bstore_nt(slot_rsrc(P.acc, P.sf, s, nbytes), vc,
+                ac[s] + (dt / 3.0) * k);
+      bstore_nt(slot_rsrc(P.out, P.sf, s, nbytes), vc, un[s] + c * k);
     }
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void epilogue(const Patch& P, int stage,
+                                         const T (&r)[NSLOT], uint32_t vc,
+                                         int32_t nbytes) {
+  double un[NSLOT], ac[NSLOT];
+  epilogue_load(P, stage, vc, nbytes, un, ac);
+  BSSN_PHASE();  // loads above, stores below
+  epilogue_store<T>(P, stage, r, vc, nbytes, un, ac);
 }
 
 // One point of one patch: everything above, for the thread's point.
