@@ -43,6 +43,7 @@ struct TileGeo<4> {
                                              // divides NSLOT, so every
                                              // phase's buffer is static
   static constexpr int BUFD = L * 256 * 2;   // doubles per buffer
+  static constexpr bool EARLY_EPI = true;    // epilogue loads at kEpiSlot
 };
 template <>
 struct TileGeo<8> {
@@ -53,6 +54,7 @@ struct TileGeo<8> {
   static constexpr int L = (G + 255) / 256;
   static constexpr int NBUF = 3;
   static constexpr int BUFD = L * 256 * 2;
+  static constexpr bool EARLY_EPI = false;  // no registers to hold them
 };
 
 static_assert(TileGeo<4>::TX == kLdsTile[0] && TileGeo<4>::TY == kLdsTile[1] &&
@@ -202,7 +204,7 @@ constexpr int kEpiSlot = BETX;
 // Loader used by point_rhs inside the pipelined kernel.  Phase p of the
 // k-th tile of a workgroup is global phase k*NSLOT + p and uses ring buffer
 // (k*NSLOT + p) mod NBUF.
-template <class Geo>
+template <class Geo, bool EARLY>
 struct LdLds {
   const Patch* P;
   double* ring;            // NBUF buffers of BUFD doubles
@@ -238,7 +240,8 @@ struct LdLds {
   __device__ __forceinline__ void enter(int s) const {
     const int p = phase_of(s);
     if (p != 0) phase(p);  // the kernel runs phase 0 itself
-    if (s == kEpiSlot) epilogue_load(*P, stage, vc_epi, nbytes, un, ac);
+    if (EARLY && s == kEpiSlot)
+      epilogue_load(*P, stage, vc_epi, nbytes, un, ac);
     const lds_double* b = (const lds_double*)buffer(p) + cidx;
     asm volatile("" : "+v"(b));
     pc = b;
@@ -256,7 +259,8 @@ struct LdLds {
     // holds at most 63, and waiting for fewer than that number is always
     // correct.  lgkmcnt(0): this wave's reads of the buffer about to be
     // refilled have completed.
-    constexpr int PE = phase_of(kEpiSlot);
+    // (without early loads, PE = NSLOT: the loads come with the stores)
+    constexpr int PE = EARLY ? phase_of(kEpiSlot) : NSLOT;
     int extra = 0;
     if (p > PE) extra = epi_loads;
     if (p <= Geo::NBUF - 2)
@@ -398,7 +402,9 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
     const bool active = x < P.n[0] && y < P.n[1] && z < P.n[2];
     const int g = P.ghost;
-    LdLds<Geo> ld;
+    // early epilogue loads where the registers allow (order 4, FP64)
+    constexpr bool early = Geo::EARLY_EPI && !MIXED;
+    LdLds<Geo, early> ld;
     ld.P = &P;
     ld.ring = ring;
     ld.sc = sc;
@@ -413,7 +419,7 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     ld.tid = tid;
     ld.stage = stage;
     ld.nbytes = nbytes;
-    ld.epi_loads = epilogue_loads(stage);
+    ld.epi_loads = early ? epilogue_loads(stage) : 0;
     ld.prev_loads = prev_loads;
     ld.prev_stores = prev_stores;
     ld.cidx = ((tz + Geo::R) * Geo::H + (ty + Geo::R)) * Geo::W + tx +
@@ -443,13 +449,23 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     if (f64) {
       double r[NSLOT];
       point_rhs<ORDER, double>(ld, P, xc, yc, zc, G, r);
-      if (active) epilogue_store<double>(P, stage, r, vc, nbytes, ld.un, ld.ac);
+      if (early) {
+        if (active)
+          epilogue_store<double>(P, stage, r, vc, nbytes, ld.un, ld.ac);
+      } else {
+        epilogue_all<double>(P, stage, r, ld.vc_epi, nbytes, active);
+      }
     } else {
       float r[NSLOT];
       point_rhs<ORDER, float>(ld, P, xc, yc, zc, G, r);
-      if (active) epilogue_store<float>(P, stage, r, vc, nbytes, ld.un, ld.ac);
+      if (early) {
+        if (active)
+          epilogue_store<float>(P, stage, r, vc, nbytes, ld.un, ld.ac);
+      } else {
+        epilogue_all<float>(P, stage, r, ld.vc_epi, nbytes, active);
+      }
     }
-    prev_loads = ld.epi_loads;
+    prev_loads = early ? ld.epi_loads : epilogue_loads(stage);
     prev_stores = __builtin_amdgcn_ballot_w64(active) != 0
                       ? epilogue_stores(stage)
                       : 0;

@@ -212,6 +212,21 @@ __device__ __forceinline__ void epilogue_store(const Patch& P, int stage,
   }
 }
 
+// The whole epilogue with the loads issued by every lane (vc_all: the
+// point's offset, or beyond the buffer for inactive lanes, which then read
+// 0 without traffic) and the stores by active lanes only; the number of
+// loads a wave issues is then exactly epilogue_loads(stage).
+template <typename T>
+__device__ __forceinline__ void epilogue_all(const Patch& P, int stage,
+                                             const T (&r)[NSLOT],
+                                             uint32_t vc_all, int32_t nbytes,
+                                             bool active) {
+  double un[NSLOT], ac[NSLOT];
+  epilogue_load(P, stage, vc_all, nbytes, un, ac);
+  BSSN_PHASE();  // loads above, stores below
+  if (active) epilogue_store<T>(P, stage, r, vc_all, nbytes, un, ac);
+}
+
 template <typename T>
 __device__ __forceinline__ void epilogue(const Patch& P, int stage,
                                          const T (&r)[NSLOT], uint32_t vc,
