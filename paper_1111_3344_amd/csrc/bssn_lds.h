@@ -204,7 +204,7 @@ constexpr int kEpiSlot = BETX;
 // Loader used by point_rhs inside the pipelined kernel.  Phase p of the
 // k-th tile of a workgroup is global phase k*NSLOT + p and uses ring buffer
 // (k*NSLOT + p) mod NBUF.
-template <class Geo, bool EARLY>
+template <class Geo, bool EARLY, bool CORNER>
 struct LdLds {
   const Patch* P;
   double* ring;            // NBUF buffers of BUFD doubles
@@ -214,7 +214,9 @@ struct LdLds {
   int nxt[3];              // next tile's origin (centre block prefetch)
   int pbase;               // (k * NSLOT) mod NBUF
   int wave, lane, tid;
-  int cidx;                // element index of the thread's centre in a box
+  int cidx;                // element index in a box of the thread's centre
+                           // or (CORNER) of its stencil corner
+                           // (x-R, y-R, z-R)
   // early epilogue loads: issued when the phase of kEpiSlot starts (the
   // algebra left after it gives their latency something to hide behind)
   int stage;
@@ -225,7 +227,7 @@ struct LdLds {
   int prev_stores;         // stores of the previous tile's epilogue in this
                            // wave (0 at the first tile)
   mutable double un[NSLOT], ac[NSLOT];
-  // this thread's centre in the current phase's buffer; set per phase
+  // this thread's cidx in the current phase's buffer; set per phase
   // through an opaque move so the compiler derives every tap from this one
   // register with immediate offsets instead of hoisting (and spilling) a
   // base address per buffer out of the tile loop
@@ -288,12 +290,18 @@ struct LdLds {
   __device__ __forceinline__ int str(int a) const {
     return a == 0 ? 1 : (a == 1 ? Geo::W : Geo::W * Geo::H);
   }
-  __device__ __forceinline__ double c(int) const { return pc[0]; }
+  // With CORNER, pc is the thread's stencil corner, so every tap is a
+  // non-negative immediate offset (fewer address adds, more ds_read2 pairs;
+  // measured faster for the mixed and the order-8 kernels, slower for the
+  // order-4 FP64 one).
+  static constexpr int kC =
+      CORNER ? Geo::R * (1 + Geo::W + Geo::W * Geo::H) : 0;
+  __device__ __forceinline__ double c(int) const { return pc[kC]; }
   __device__ __forceinline__ double ax(int, int a, int k) const {
-    return pc[k * str(a)];
+    return pc[kC + k * str(a)];
   }
   __device__ __forceinline__ double pl(int, int a, int i, int b, int j) const {
-    return pc[i * str(a) + j * str(b)];
+    return pc[kC + i * str(a) + j * str(b)];
   }
 };
 
@@ -402,9 +410,11 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
     const bool active = x < P.n[0] && y < P.n[1] && z < P.n[2];
     const int g = P.ghost;
-    // early epilogue loads where the registers allow (order 4, FP64)
+    // early epilogue loads where the registers allow (order 4, FP64);
+    // corner-based tap addressing for the mixed and order-8 kernels
     constexpr bool early = Geo::EARLY_EPI && !MIXED;
-    LdLds<Geo, early> ld;
+    constexpr bool corner = MIXED || ORDER == 8;
+    LdLds<Geo, early, corner> ld;
     ld.P = &P;
     ld.ring = ring;
     ld.sc = sc;
@@ -422,8 +432,8 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     ld.epi_loads = early ? epilogue_loads(stage) : 0;
     ld.prev_loads = prev_loads;
     ld.prev_stores = prev_stores;
-    ld.cidx = ((tz + Geo::R) * Geo::H + (ty + Geo::R)) * Geo::W + tx +
-              Geo::R + 1;
+    ld.cidx = (tz * Geo::H + ty) * Geo::W + tx + 1 +
+              (corner ? 0 : Geo::R * (1 + Geo::W + Geo::W * Geo::H));
     const uint32_t vc = active ? uint32_t(z + g) * sz8 + uint32_t(y + g) * sy8 +
                                      uint32_t(x + g) * 8u
                                : 0u;
