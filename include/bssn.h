@@ -192,14 +192,20 @@ typedef struct bssn_batch_plan bssn_batch_plan;
  *             step
  *   a[p], b[p]  device scratch state buffers with the same ghosts as u[p]
  *   acc[p]    device scratch state buffer (ghosts unused)
- * autotune = 1 times candidate tile shapes per patch size class on the
- * given buffers (their contents are not modified in a way visible after the
- * plan is built: tuning runs stage 0 only, which writes a and acc) and keeps
- * the fastest; 0 uses the default shape.  The plan records all work as one
- * persistent kernel per RK4 stage and captures the four stages of a step
- * in a hipGraph.  It stores copies of the pointer arrays; the buffers must
- * stay allocated while the plan lives.
- * Errors: BSSN_EINVAL, BSSN_ENOMEM, BSSN_EHIP. */
+ * autotune = 1 times every kernel tile (shape and z-block depth, see
+ * batch_patches_describe) the layout allows, per patch size class, on the
+ * given buffers, and keeps the fastest (tuning runs stage 0 only, which
+ * writes a and acc: nothing visible once the plan is built); 0 uses the
+ * default tile (the LDS-pipelined kernel where the layout allows it);
+ * BSSN_BATCH_TILE(v) uses tile v (0..4, in the order listed under
+ * batch_patches_describe) for every class.  The plan records the work of
+ * each tile in use as one launch per RK4 stage (a persistent kernel for the
+ * LDS tile) and captures the four stages of a step in a hipGraph.  It
+ * stores copies of the pointer arrays; the buffers must stay allocated
+ * while the plan lives.
+ * Errors: BSSN_EINVAL (also for a forced tile the layout does not allow),
+ * BSSN_ENOMEM, BSSN_EHIP. */
+#define BSSN_BATCH_TILE(v) (0x100 | (v))
 int batch_patches_plan(int npatch, const bssn_grid* grids,
                        const bssn_params* params, double* const* u,
                        double* const* a, double* const* b,
@@ -214,9 +220,14 @@ int batch_patches(bssn_batch_plan* plan, int nsteps, void* stream);
  * patch and stage (the baseline the batched path is measured against). */
 int batch_patches_unbatched(bssn_batch_plan* plan, int nsteps, void* stream);
 
-/* Tile shape chosen for each size class: writes up to max_classes entries of
- * (class extent, tile_x, tile_y) triples into host array out; returns the
- * number of classes (>= 0) or an error code. */
+/* Kernel tile chosen for each size class (classes in increasing extent;
+ * a class holds the patches whose largest extent rounds up to the same
+ * multiple of 16): writes up to max_classes entries of (class extent,
+ * tile_x, tile_y, z-block depth) into host array out (4 int32 each).
+ * The tiles: 0 (16, 4, 4) the LDS-pipelined kernel; 1 (64, 4, 1),
+ * 2 (32, 8, 1), 3 (64, 4, 4), 4 (32, 8, 4) the direct kernel, one
+ * workgroup per tile of one plane or of a 4-plane z-block.  Returns the number of classes (>= 0,
+ * possibly more than max_classes) or an error code. */
 int batch_patches_describe(const bssn_batch_plan* plan, int max_classes,
                            int32_t* out);
 

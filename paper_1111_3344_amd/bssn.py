@@ -25,6 +25,11 @@ BSSN_BC_STATIC, BSSN_BC_PERIODIC = 0, 1
 BSSN_PATH_AUTO, BSSN_PATH_DIRECT = 0, 1
 
 
+def BSSN_BATCH_TILE(v):
+    """batch_patches_plan autotune value forcing tile v for every class."""
+    return 0x100 | int(v)
+
+
 class BssnError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} (code {code})")
@@ -234,7 +239,7 @@ def batch_patches_plan(grids, params, u, a, b, acc, dt, autotune=True,
     h = ctypes.c_void_p()
     _check(lib().batch_patches_plan(n, G, ctypes.byref(_params(params)),
                                     arrs[0], arrs[1], arrs[2], arrs[3],
-                                    float(dt), int(bool(autotune)),
+                                    float(dt), int(autotune),
                                     ctypes.byref(h), _stream(stream)))
     return BatchPlan(h, (u, a, b, acc))
 
@@ -249,11 +254,12 @@ def batch_patches_unbatched(plan, nsteps, stream=None):
 
 
 def batch_patches_describe(plan, max_classes=64):
-    out = (ctypes.c_int32 * (3 * max_classes))()
+    """[(class extent, tile_x, tile_y, z-block depth), ...]"""
+    out = (ctypes.c_int32 * (4 * max_classes))()
     n = lib().batch_patches_describe(plan.handle, max_classes, out)
     if n < 0:
         raise BssnError(n, bssn_last_error())
-    return [tuple(out[3 * i:3 * i + 3]) for i in range(n)]
+    return [tuple(out[4 * i:4 * i + 4]) for i in range(min(n, max_classes))]
 
 
 def batch_patches_destroy(plan):

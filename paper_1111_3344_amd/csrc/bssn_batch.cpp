@@ -11,7 +11,8 @@
 //            whole patches are assigned to XCDs (balanced by tile count) and
 //            each patch's tiles are split evenly over the workgroups of its
 //            XCD, one item (patch, first tile, end tile) per workgroup;
-//   VAR_D*   one item per direct-kernel workgroup (patch, x0, y0, z).
+//   VAR_D*   one item per direct-kernel workgroup (patch, x0, y0, z0): a
+//            64 x 4 or 32 x 8 tile of one plane or of a 4-plane z-block.
 // The four stages of an RK4 step (one launch per variant in use per stage)
 // are captured once into a hipGraph; batch_patches replays it per step.
 #include <hip/hip_runtime.h>
@@ -32,7 +33,6 @@ namespace bssn {
 namespace {
 
 constexpr int kMaxPatches = 1 << 16;
-constexpr int kDirectBX[NVAR] = {0, 64, 32};
 constexpr int kTuneReps = 3;
 
 int class_extent(const bssn_grid& g) {
@@ -151,12 +151,13 @@ int build_group(const std::vector<bssn_grid>& grids,
     G.wstart[nwg] = int32_t(G.lds.size());
     return BSSN_OK;
   }
-  const int bx = kDirectBX[variant], by = 256 / bx;
+  const int bx = kVarTile[variant][0], by = kVarTile[variant][1];
+  const int bz = kVarTile[variant][2];
   int64_t count = 0;
   for (int p : pids) {
     const bssn_grid& g = grids[p];
     count += int64_t((g.n[0] + bx - 1) / bx) * ((g.n[1] + by - 1) / by) *
-             g.n[2];
+             ((g.n[2] + bz - 1) / bz);
   }
   if (count >= (int64_t(1) << 31) - 1)
     return fail(BSSN_EUNSUPPORTED, "batch: %lld workgroups exceed one launch",
@@ -164,10 +165,10 @@ int build_group(const std::vector<bssn_grid>& grids,
   G.direct.reserve(size_t(count));
   for (int p : pids) {
     const bssn_grid& g = grids[p];
-    for (int z = 0; z < g.n[2]; ++z)
+    for (int z0 = 0; z0 < g.n[2]; z0 += bz)
       for (int y0 = 0; y0 < g.n[1]; y0 += by)
         for (int x0 = 0; x0 < g.n[0]; x0 += bx)
-          G.direct.push_back(DirectItem{p, x0, y0, z});
+          G.direct.push_back(DirectItem{p, x0, y0, z0});
   }
   return BSSN_OK;
 }
@@ -354,7 +355,13 @@ int plan_build(bssn_batch_plan* P, int autotune, hipStream_t st) {
         lds_ok = lds_ok && variant_ok(P->hp[s][p], P->order, VAR_LDS);
     const int dflt = lds_ok ? VAR_LDS : (c.extent > 32 ? VAR_D64 : VAR_D32);
     c.variant = dflt;
-    if (autotune) {
+    if ((autotune & ~0xff) == 0x100) {
+      c.variant = autotune & 0xff;
+      if (c.variant == VAR_LDS && !lds_ok)
+        return fail(BSSN_EINVAL, "forced LDS tile: a patch of class %d has "
+                    "buffers the LDS kernel cannot address in 16-byte "
+                    "granules", c.extent);
+    } else if (autotune == 1) {
       // patch records must be on the device for the trial launches
       if (!P->dmem) {
         hipError_t e = hipMalloc((void**)&P->dmem, pbytes);
@@ -438,8 +445,11 @@ int batch_patches_plan(int npatch, const bssn_grid* grids,
   if (!grids || !u || !a || !b || !acc)
     return fail(BSSN_EINVAL, "grids and the buffer arrays must be non-NULL");
   if (!std::isfinite(dt)) return fail(BSSN_EINVAL, "dt is not finite");
-  if (autotune != 0 && autotune != 1)
-    return fail(BSSN_EINVAL, "autotune = %d (0 or 1)", autotune);
+  const bool forced = (autotune & ~0xff) == 0x100;
+  if (autotune != 0 && autotune != 1 &&
+      !(forced && (autotune & 0xff) < NVAR))
+    return fail(BSSN_EINVAL, "autotune = %d (0, 1 or BSSN_BATCH_TILE(0..%d))",
+                autotune, NVAR - 1);
   for (int p = 0; p < npatch; ++p) {
     if ((rc = check_grid(&grids[p], params->fd_order)))
       return fail(rc, "patch %d: %s", p, bssn_last_error());
@@ -537,18 +547,12 @@ int batch_patches_describe(const bssn_batch_plan* plan, int max_classes,
                            int32_t* out) {
   if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
   if (max_classes < 0 || (max_classes > 0 && !out))
-    return fail(BSSN_EINVAL, "out must hold 3 * max_classes entries");
+    return fail(BSSN_EINVAL, "out must hold 4 * max_classes entries");
   const int n = int(plan->classes.size());
   for (int i = 0; i < n && i < max_classes; ++i) {
     const auto& c = plan->classes[i];
-    out[3 * i] = c.extent;
-    if (c.variant == VAR_LDS) {
-      out[3 * i + 1] = kLdsTile[0];
-      out[3 * i + 2] = kLdsTile[1];
-    } else {
-      out[3 * i + 1] = kDirectBX[c.variant];
-      out[3 * i + 2] = 256 / kDirectBX[c.variant];
-    }
+    out[4 * i] = c.extent;
+    for (int a = 0; a < 3; ++a) out[4 * i + 1 + a] = kVarTile[c.variant][a];
   }
   return n;
 }

@@ -48,18 +48,29 @@ struct Gauge {
 // Work items of the batched kernels.  LDS kernel: a run of tiles [tlo, thi)
 // of one patch whose tile grid is ntx x nty x ntz (tiles numbered z fastest
 // within an (x, y) column).  Direct kernel: the workgroup-shaped tile at
-// (x0, y0) of plane z of one patch.
+// (x0, y0) of a z-block of planes of one patch.
 struct LdsItem {
   int32_t patch, tlo, thi, ntx, nty, ntz;
 };
 struct DirectItem {
-  int32_t patch, x0, y0, z;
+  int32_t patch, x0, y0, z0;  // planes z0 .. z0 + depth - 1
 };
 
 // Kernel variants a batch plan chooses between, per patch size class:
 // the LDS-pipelined persistent kernel (16 x 4 x 4 tiles) and the direct-load
-// kernel with 64 x 4 or 32 x 8 workgroups.
-enum : int { VAR_LDS = 0, VAR_D64 = 1, VAR_D32 = 2, NVAR = 3 };
+// kernel with 64 x 4 or 32 x 8 workgroups, each workgroup doing one plane
+// or marching through a z-block of 4 planes.
+enum : int {
+  VAR_LDS = 0,
+  VAR_D64 = 1,
+  VAR_D32 = 2,
+  VAR_D64Z4 = 3,
+  VAR_D32Z4 = 4,
+  NVAR = 5
+};
 constexpr int kLdsTile[3] = {16, 4, 4};  // LDS kernel tile (x, y, z)
+// tile (x, y, z-block depth) of each variant
+constexpr int kVarTile[NVAR][3] = {
+    {16, 4, 4}, {64, 4, 1}, {32, 8, 1}, {64, 4, 4}, {32, 8, 4}};
 
 }  // namespace bssn

@@ -615,9 +615,11 @@ hipError_t launch_patch_t(const Patch& P, const Gauge& G, int stage,
     case VAR_LDS:
       return launch_stage_lds<ORDER>(P, G, stage, precision, nwg, st);
     case VAR_D64:
+    case VAR_D64Z4:  // per patch, one plane per workgroup (same results)
       return launch_stage_variant<ORDER, false>(P, G, stage, precision, 64,
                                                 st);
     case VAR_D32:
+    case VAR_D32Z4:
       return launch_stage_variant<ORDER, false>(P, G, stage, precision, 32,
                                                 st);
   }
@@ -626,7 +628,7 @@ hipError_t launch_patch_t(const Patch& P, const Gauge& G, int stage,
 
 template <int ORDER>
 bool variant_ok_t(const Patch& P, int variant) {
-  if (variant != VAR_LDS) return variant == VAR_D64 || variant == VAR_D32;
+  if (variant != VAR_LDS) return variant > VAR_LDS && variant < NVAR;
   Patch q = P;
   const double* bufs[4] = {P.u_s, P.u_n, P.acc, P.out};
   for (const double* b : bufs) {
@@ -650,11 +652,11 @@ hipError_t launch_batch_t(const BatchLaunch& B, const Gauge& G, int stage,
                          dim3(256), 0, st, B.patches, it, B.wstart, G, stage);
     return hipGetLastError();
   }
-  if (B.variant != VAR_D64 && B.variant != VAR_D32)
-    return hipErrorInvalidValue;
+  if (B.variant <= VAR_LDS || B.variant >= NVAR) return hipErrorInvalidValue;
   return launch_direct_batch<ORDER>(
       B.patches, static_cast<const DirectItem*>(B.items), B.nitems,
-      B.variant == VAR_D64 ? 64 : 32, G, stage, precision, st);
+      kVarTile[B.variant][0], kVarTile[B.variant][2], G, stage, precision,
+      st);
 }
 
 }  // namespace bssn

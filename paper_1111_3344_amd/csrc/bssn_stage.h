@@ -314,16 +314,22 @@ __global__ void __launch_bounds__(256)
       blockIdx.y * blockDim.y + threadIdx.y, blockIdx.z);
 }
 
-// Many static patches: block b takes work item b = (patch, x0, y0, z).
+// Many static patches: block b takes work item b = (patch, x0, y0, z0) and
+// marches through planes z0 .. z0 + depth - 1 (those inside the patch), so
+// the z-neighbour rows of its stencils are hits in the caches.
 template <int ORDER, int TILES>
 __global__ void __launch_bounds__(256)
     k_stage_direct_batch(const Patch* __restrict__ patches,
                          const DirectItem* __restrict__ work, const Gauge G,
-                         const int stage) {
+                         const int stage, const int depth) {
   const DirectItem w = work[blockIdx.x];
   const Patch P = patches[w.patch];
-  stage_block<ORDER, false, TILES>(P, G, stage, w.x0 + threadIdx.x,
-                                   w.y0 + threadIdx.y, w.z);
+  for (int dz = 0; dz < depth; ++dz) {
+    const int z = w.z0 + dz;
+    if (z >= P.n[2]) break;  // uniform over the workgroup
+    stage_block<ORDER, false, TILES>(P, G, stage, w.x0 + threadIdx.x,
+                                     w.y0 + threadIdx.y, z);
+  }
 }
 
 // ---- host-side launch -------------------------------------------------------------
@@ -354,17 +360,17 @@ hipError_t launch_stage_variant(const Patch& P, const Gauge& G, int stage,
 
 template <int ORDER>
 hipError_t launch_direct_batch(const Patch* patches, const DirectItem* work,
-                               int nwork, int bx, const Gauge& G, int stage,
-                               int precision, hipStream_t st) {
+                               int nwork, int bx, int depth, const Gauge& G,
+                               int stage, int precision, hipStream_t st) {
   const dim3 blk(bx, 256 / bx, 1);
   if (precision == 0) {
     hipLaunchKernelGGL((k_stage_direct_batch<ORDER, TILE_ALL>), dim3(nwork),
-                       blk, 0, st, patches, work, G, stage);
+                       blk, 0, st, patches, work, G, stage, depth);
   } else {
     hipLaunchKernelGGL((k_stage_direct_batch<ORDER, TILE_FP32>), dim3(nwork),
-                       blk, 0, st, patches, work, G, stage);
+                       blk, 0, st, patches, work, G, stage, depth);
     hipLaunchKernelGGL((k_stage_direct_batch<ORDER, TILE_FP64>), dim3(nwork),
-                       blk, 0, st, patches, work, G, stage);
+                       blk, 0, st, patches, work, G, stage, depth);
   }
   return hipGetLastError();
 }

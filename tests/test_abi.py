@@ -127,6 +127,8 @@ def test_batch_plan_validation():
     assert _plan([g], prm, out=False) == B.BSSN_EINVAL
     assert _plan([g], prm, dt=float("inf")) == B.BSSN_EINVAL
     assert _plan([g], prm, autotune=2) == B.BSSN_EINVAL
+    assert _plan([g], prm, autotune=B.BSSN_BATCH_TILE(5)) == B.BSSN_EINVAL
+    assert _plan([g], prm, autotune=0x200) == B.BSSN_EINVAL
     gp = I.cell_centred(8, -1, 1, 3, I.BC_PERIODIC)
     assert _plan([g, gp], prm) == B.BSSN_EINVAL
     assert "patch 1" in B.bssn_last_error()

@@ -90,7 +90,7 @@ def test_batched_lds_equals_rk4_stage_bitwise(B):
     dt = 0.03125
     plan = B.batch_patches_plan(grids, prm, *bufs, dt, autotune=0)
     classes = B.batch_patches_describe(plan)
-    assert all((tx, ty) == (16, 4) for _, tx, ty in classes)
+    assert all(c[1:] == (16, 4, 4) for c in classes)
     B.batch_patches(plan, 1)
     got = results(grids, bufs[0])
     for p, (g, x) in enumerate(zip(grids, us)):
@@ -131,8 +131,9 @@ def test_describe_classes(B):
     assert ext == sorted(set(ext))
     want = sorted({(max(g.n) + 15) // 16 * 16 for g in grids})
     assert ext == want
-    assert all((tx, ty) in ((16, 4), (64, 4), (32, 8)) for _, tx, ty in classes)
-    assert B.batch_patches_describe(plan, max_classes=1)[0] == classes[0]
+    assert all(c[1:] in ((16, 4, 4), (64, 4, 1), (32, 8, 1), (64, 4, 4),
+                         (32, 8, 4)) for c in classes)
+    assert B.batch_patches_describe(plan, max_classes=1) == classes[:1]
     plan.destroy()
 
 
@@ -153,4 +154,61 @@ def test_stale_plan_after_free(B):
         with pytest.raises(B.BssnError) as ei:
             fn(plan, 1)
         assert ei.value.code == B.BSSN_ESTALE
+    plan.destroy()
+
+
+def test_large_patch_spread_over_xcds_bitwise(B):
+    """A patch with more than an eighth of all tiles is split over every
+    XCD; the rest go whole to the least-loaded XCD."""
+    h = 0.125
+    sizes = [(96, 96, 96), (20, 24, 28), (33, 17, 25), (24, 24, 24),
+             (40, 21, 19)]
+    grids, us = [], []
+    for i, n in enumerate(sizes):
+        origin = tuple(-0.5 * n[a] * h + 0.5 * h for a in range(3))
+        g = I.GridSpec(n, 3, (h, h, h), origin, I.BC_STATIC)
+        grids.append(g)
+        us.append(I.brill_lindquist(g, (0.4 + 0.1 * i,), ((0.3, -0.2, 0.1),)))
+    bufs = device_set(B, us)
+    plan = B.batch_patches_plan(grids, B.Params(), *bufs, 0.03125,
+                                autotune=0)
+    B.batch_patches(plan, 1)
+    got = results(grids, bufs[0])
+    reset(bufs, us)
+    B.batch_patches_unbatched(plan, 1)
+    ref = results(grids, bufs[0])
+    for p, (x, y) in enumerate(zip(got, ref)):
+        assert np.array_equal(x, y), f"patch {p} differs"
+    plan.destroy()
+
+
+@pytest.mark.parametrize("tile", range(5))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_forced_tiles_bitwise_and_oracle(B, tile, precision):
+    """Every kernel tile (LDS 16x4x4; direct 64x4 and 32x8, one plane or a
+    4-plane z-block) batched == per-patch bitwise; FP64 also == oracle."""
+    grids, us = host_set(5, 200 + tile, 17, 40)
+    bufs = device_set(B, us)
+    prm = B.Params(precision=precision)
+    dt = 0.03125
+    plan = B.batch_patches_plan(grids, prm, *bufs, dt,
+                                autotune=B.BSSN_BATCH_TILE(tile))
+    want = [(16, 4, 4), (64, 4, 1), (32, 8, 1), (64, 4, 4), (32, 8, 4)][tile]
+    assert all(c[1:] == want for c in B.batch_patches_describe(plan))
+    B.batch_patches(plan, 1)
+    got = results(grids, bufs[0])
+    reset(bufs, us)
+    B.batch_patches_unbatched(plan, 1)
+    ref = results(grids, bufs[0])
+    for p, (x, y) in enumerate(zip(got, ref)):
+        assert np.array_equal(x, y), f"patch {p} differs"
+    if precision == 0:
+        for p, (g, x) in enumerate(zip(grids, us)):
+            o = g.interior(O.rk4_step(g, O.params(), dt, x))
+            u0 = g.interior(x)
+            d = np.abs(o - u0).reshape(25, -1).max(1)
+            m = np.abs(o).reshape(25, -1).max(1)
+            tol = 1e-12 * d + 8 * EPS * np.maximum(m, 1e-300)
+            err = np.abs(got[p] - o).reshape(25, -1).max(1)
+            assert (err <= tol).all(), (p, err / np.maximum(tol, 1e-300))
     plan.destroy()

@@ -110,6 +110,16 @@ CASES = {
         lambda: I.cell_centred(40, -24, 24, 5),
         lambda g: I.brill_lindquist(g, (0.6, 0.4), ((4, 0, 0), (-4, 0, 0))),
         dict(fd_order=8)),
+    # tile grid 8 x 16 x 10: the LDS kernel takes its blocked walk (4x4x2
+    # blocks, one per XCD), with a ragged x edge (124 = 7.75 tiles)
+    "smooth-static-blocked": (
+        lambda: I.GridSpec((124, 64, 40), 3, (0.1, 0.11, 0.12),
+                           (-6.1, -3.5, -2.4), I.BC_STATIC),
+        lambda g: I.smooth_random(g, seed=12), {}),
+    "order8-smooth-blocked": (
+        lambda: I.GridSpec((124, 64, 40), 5, (0.1, 0.11, 0.12),
+                           (-6.1, -3.5, -2.4), I.BC_STATIC),
+        lambda g: I.smooth_random(g, seed=13), dict(fd_order=8)),
 }
 
 
@@ -147,7 +157,8 @@ def test_rhs_matches_oracle(B, case, path):
     ("smooth-static-ragged", 2, 0.02),
     ("smooth-periodic", 2, 0.02),
     ("bl-two-punctures-48", 2, 0.1),
-    ("order8-smooth-static", 1, 0.02)])
+    ("order8-smooth-static", 1, 0.02),
+    ("smooth-static-blocked", 2, 0.02)])
 def test_rk4_steps_match_oracle(B, case, nsteps, dt, path):
     gfn, dfn, kw = CASES[case]
     g = gfn()
