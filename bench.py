@@ -293,9 +293,11 @@ def traffic_bytes(kv):
 
 def batched(B, torch, steps, warmup, npatch=256):
     """256 uneven static patches (interiors U{24..96} per axis, h = 0.125,
-    one Brill-Lindquist puncture each): a batch plan (autotuned) advanced
-    with batch_patches (one graph replay per RK4 step) against one launch
-    per patch and stage, FP64 and mixed."""
+    one Brill-Lindquist puncture each): a batch plan advanced with
+    batch_patches (one graph replay per RK4 step) against one launch per
+    patch and stage, FP64 and mixed.  The plan is autotuned (tile per size
+    class and launch mode), and a second plan forced to the persistent
+    work-list mode is timed too."""
     from paper_1111_3344_amd import inputs as I
     specs = I.patches(npatch)
     grids = [g for g, _, _ in specs]
@@ -311,16 +313,23 @@ def batched(B, torch, steps, warmup, npatch=256):
     for label, prec in (("f64", B.BSSN_FP64), ("mixed", B.BSSN_MIXED)):
         plan = B.batch_patches_plan(grids, B.Params(precision=prec), u, a, b,
                                     acc, 0.03125, autotune=True)
-        r = {"classes": [list(c) for c in B.batch_patches_describe(plan)]}
-        for mode, fn in (("batched", B.batch_patches),
-                         ("per_patch", B.batch_patches_unbatched)):
-            fn(plan, warmup, stream)
+        r = {"classes": [list(c) for c in B.batch_patches_describe(plan)],
+             "launch_mode": ("per-patch graph" if
+                             B.batch_patches_launch_mode(plan) else
+                             "persistent work lists")}
+        forced = B.batch_patches_plan(grids, B.Params(precision=prec), u, a,
+                                      b, acc, 0.03125,
+                                      autotune=B.BSSN_BATCH_TILE(0))
+        for mode, fn, pl in (("batched", B.batch_patches, plan),
+                             ("batched_persistent", B.batch_patches, forced),
+                             ("per_patch", B.batch_patches_unbatched, plan)):
+            fn(pl, warmup, stream)
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             t0 = time.perf_counter()
             e0.record(stream)
-            fn(plan, steps, stream)
+            fn(pl, steps, stream)
             e1.record(stream)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
@@ -330,6 +339,7 @@ def batched(B, torch, steps, warmup, npatch=256):
                        "hbm_frac": round(3200.0 * N * steps / wall / 1e9 /
                                          HBM_PEAK_GBS, 4)}
         plan.destroy()
+        forced.destroy()
         out[label] = r
     return out
 

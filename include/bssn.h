@@ -198,14 +198,19 @@ typedef struct bssn_batch_plan bssn_batch_plan;
  * writes a and acc: nothing visible once the plan is built); 0 uses the
  * default tile (the LDS-pipelined kernel where the layout allows it);
  * BSSN_BATCH_TILE(v) uses tile v (0..4, in the order listed under
- * batch_patches_describe) for every class.  The plan records the work of
- * each tile in use as one launch per RK4 stage (a persistent kernel for the
- * LDS tile) and captures the four stages of a step in a hipGraph.  It
- * stores copies of the pointer arrays; the buffers must stay allocated
- * while the plan lives.
+ * batch_patches_describe) for every class.  The plan captures the four
+ * stages of a step in a hipGraph, in one of two launch modes: persistent
+ * (the work of each tile in use as one launch per RK4 stage over a device
+ * work list; a persistent kernel for the LDS tile) or per patch (one launch
+ * per patch and stage, the kernels batch_patches_unbatched uses).
+ * autotune = 1 also times both modes (stage 0) and keeps the faster; the
+ * flag BSSN_BATCH_PER_PATCH (alone or with BSSN_BATCH_TILE) selects the per
+ * patch mode, otherwise the mode is persistent.  The plan stores copies of
+ * the pointer arrays; the buffers must stay allocated while it lives.
  * Errors: BSSN_EINVAL (also for a forced tile the layout does not allow),
  * BSSN_ENOMEM, BSSN_EHIP. */
 #define BSSN_BATCH_TILE(v) (0x100 | (v))
+#define BSSN_BATCH_PER_PATCH 0x200
 int batch_patches_plan(int npatch, const bssn_grid* grids,
                        const bssn_params* params, double* const* u,
                        double* const* a, double* const* b,
@@ -230,6 +235,10 @@ int batch_patches_unbatched(bssn_batch_plan* plan, int nsteps, void* stream);
  * possibly more than max_classes) or an error code. */
 int batch_patches_describe(const bssn_batch_plan* plan, int max_classes,
                            int32_t* out);
+
+/* Launch mode of the plan's graph: 0 (persistent work lists) or
+ * BSSN_BATCH_PER_PATCH; an error code for a NULL plan. */
+int batch_patches_launch_mode(const bssn_batch_plan* plan);
 
 /* Release the plan (its graph, work list and device copies). */
 int batch_patches_destroy(bssn_batch_plan* plan);

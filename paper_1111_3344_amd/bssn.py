@@ -25,6 +25,9 @@ BSSN_BC_STATIC, BSSN_BC_PERIODIC = 0, 1
 BSSN_PATH_AUTO, BSSN_PATH_DIRECT = 0, 1
 
 
+BSSN_BATCH_PER_PATCH = 0x200
+
+
 def BSSN_BATCH_TILE(v):
     """batch_patches_plan autotune value forcing tile v for every class."""
     return 0x100 | int(v)
@@ -108,6 +111,7 @@ def lib():
             L.batch_patches_describe.argtypes = [vp, ctypes.c_int,
                                                  P(ctypes.c_int32)]
             L.batch_patches_destroy.argtypes = [vp]
+            L.batch_patches_launch_mode.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -260,6 +264,13 @@ def batch_patches_describe(plan, max_classes=64):
     if n < 0:
         raise BssnError(n, bssn_last_error())
     return [tuple(out[4 * i:4 * i + 4]) for i in range(min(n, max_classes))]
+
+
+def batch_patches_launch_mode(plan):
+    m = lib().batch_patches_launch_mode(plan.handle)
+    if m < 0:
+        raise BssnError(m, bssn_last_error())
+    return m
 
 
 def batch_patches_destroy(plan):

@@ -222,6 +222,8 @@ struct bssn_batch_plan {
   std::vector<int> var_of_patch;
   char* dmem = nullptr;               // Patch[4][np], then work lists
   std::vector<BatchLaunch> launches;  // one per variant in use (stage-free)
+  int mode = 0;                       // kPersistent or kPerPatch
+  float mode_ms[2] = {-1.f, -1.f};    // tuned stage-0 times per mode
   hipStream_t cs = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -265,24 +267,98 @@ int check_fresh(const bssn_batch_plan* plan) {
   return BSSN_OK;
 }
 
-int record_graph(bssn_batch_plan* P) {
-  hipError_t e = hipStreamCreateWithFlags(&P->cs, hipStreamNonBlocking);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
-  e = hipStreamBeginCapture(P->cs, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-  hipError_t le = hipSuccess;
-  for (int s = 0; s < 4 && le == hipSuccess; ++s)
-    for (BatchLaunch L : P->launches) {
-      L.patches = P->dpatches(s);
-      le = launch_batch(L, P->G, P->order, s, P->precision, P->cs);
-      if (le != hipSuccess) break;
+// Launch modes of a plan's graph: the persistent work-list kernels (one
+// launch per tile in use per stage), or one launch per patch and stage
+// (the same kernels batch_patches_unbatched uses).
+enum : int { kPersistent = 0, kPerPatch = 1 };
+
+hipError_t enqueue_stages(bssn_batch_plan* P, int mode, int s0, int s1,
+                          hipStream_t st) {
+  const int nwg = persistent_groups();
+  for (int s = s0; s < s1; ++s) {
+    if (mode == kPersistent) {
+      for (BatchLaunch L : P->launches) {
+        L.patches = P->dpatches(s);
+        hipError_t e = launch_batch(L, P->G, P->order, s, P->precision, st);
+        if (e != hipSuccess) return e;
+      }
+    } else {
+      for (int p = 0; p < P->np; ++p) {
+        hipError_t e = launch_patch(P->hp[s][p], P->G, P->order, s,
+                                    P->precision, P->var_of_patch[p], nwg, st);
+        if (e != hipSuccess) return e;
+      }
     }
-  e = hipStreamEndCapture(P->cs, &P->graph);
-  if (le != hipSuccess) return hip_fail(le, "batch stage capture");
+  }
+  return hipSuccess;
+}
+
+// Captures stages [s0, s1) in `mode` on the plan's private stream.
+int capture(bssn_batch_plan* P, int mode, int s0, int s1, hipGraph_t* g,
+            hipGraphExec_t* x) {
+  *g = nullptr;
+  *x = nullptr;
+  hipError_t e = hipStreamBeginCapture(P->cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  const hipError_t le = enqueue_stages(P, mode, s0, s1, P->cs);
+  e = hipStreamEndCapture(P->cs, g);
+  if (le != hipSuccess) {
+    if (*g) (void)hipGraphDestroy(*g);
+    *g = nullptr;
+    return hip_fail(le, "batch stage capture");
+  }
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(x, *g, nullptr, nullptr, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
   return BSSN_OK;
+}
+
+// Milliseconds of one replay of a stage-0 graph of `mode` (best of
+// kTuneReps after a warm-up), or < 0 with *rc set on failure.
+float time_mode(bssn_batch_plan* P, int mode, hipStream_t st, int* rc) {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  if ((*rc = capture(P, mode, 0, 1, &g, &x))) return -1.f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float best = -1.f;
+  for (int r = 0; r <= kTuneReps && e == hipSuccess; ++r) {
+    e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = hipGraphLaunch(x, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && r > 0 && (best < 0.f || ms < best)) best = ms;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(x);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    *rc = hip_fail(e, "launch-mode timing");
+    return -1.f;
+  }
+  *rc = BSSN_OK;
+  return best;
+}
+
+// The step graph: launch mode (timed when tuning), then stages 0..3.
+int record_graph(bssn_batch_plan* P, int autotune, hipStream_t st) {
+  hipError_t e = hipStreamCreateWithFlags(&P->cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+  P->mode = (autotune & BSSN_BATCH_PER_PATCH) ? kPerPatch : kPersistent;
+  if (autotune == 1) {
+    for (int m = 0; m < 2; ++m) {
+      int rc = BSSN_OK;
+      P->mode_ms[m] = time_mode(P, m, st, &rc);
+      if (rc) return rc;
+    }
+    P->mode = P->mode_ms[kPerPatch] < P->mode_ms[kPersistent] ? kPerPatch
+                                                              : kPersistent;
+  }
+  return capture(P, P->mode, 0, 4, &P->graph, &P->exec);
 }
 
 // Milliseconds of one batched stage-0 launch of variant v over pids (best
@@ -355,7 +431,7 @@ int plan_build(bssn_batch_plan* P, int autotune, hipStream_t st) {
         lds_ok = lds_ok && variant_ok(P->hp[s][p], P->order, VAR_LDS);
     const int dflt = lds_ok ? VAR_LDS : (c.extent > 32 ? VAR_D64 : VAR_D32);
     c.variant = dflt;
-    if ((autotune & ~0xff) == 0x100) {
+    if (autotune & 0x100) {
       c.variant = autotune & 0xff;
       if (c.variant == VAR_LDS && !lds_ok)
         return fail(BSSN_EINVAL, "forced LDS tile: a patch of class %d has "
@@ -423,7 +499,7 @@ int plan_build(bssn_batch_plan* P, int autotune, hipStream_t st) {
     P->launches.push_back(L);
     cur += group_bytes(g);
   }
-  return record_graph(P);
+  return record_graph(P, autotune, st);
 }
 
 }  // namespace
@@ -445,11 +521,16 @@ int batch_patches_plan(int npatch, const bssn_grid* grids,
   if (!grids || !u || !a || !b || !acc)
     return fail(BSSN_EINVAL, "grids and the buffer arrays must be non-NULL");
   if (!std::isfinite(dt)) return fail(BSSN_EINVAL, "dt is not finite");
-  const bool forced = (autotune & ~0xff) == 0x100;
-  if (autotune != 0 && autotune != 1 &&
-      !(forced && (autotune & 0xff) < NVAR))
-    return fail(BSSN_EINVAL, "autotune = %d (0, 1 or BSSN_BATCH_TILE(0..%d))",
-                autotune, NVAR - 1);
+  {
+    const int flags = autotune & ~0xff, v = autotune & 0xff;
+    const bool ok =
+        autotune == 0 || autotune == 1 ||
+        ((flags & ~(0x100 | BSSN_BATCH_PER_PATCH)) == 0 && flags != 0 &&
+         ((flags & 0x100) ? v < NVAR : v == 0));
+    if (!ok)
+      return fail(BSSN_EINVAL, "autotune = %d: 0, 1, BSSN_BATCH_TILE(0..%d) "
+                  "and/or BSSN_BATCH_PER_PATCH", autotune, NVAR - 1);
+  }
   for (int p = 0; p < npatch; ++p) {
     if ((rc = check_grid(&grids[p], params->fd_order)))
       return fail(rc, "patch %d: %s", p, bssn_last_error());
@@ -555,6 +636,11 @@ int batch_patches_describe(const bssn_batch_plan* plan, int max_classes,
     for (int a = 0; a < 3; ++a) out[4 * i + 1 + a] = kVarTile[c.variant][a];
   }
   return n;
+}
+
+int batch_patches_launch_mode(const bssn_batch_plan* plan) {
+  if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
+  return plan->mode == kPerPatch ? BSSN_BATCH_PER_PATCH : 0;
 }
 
 int batch_patches_destroy(bssn_batch_plan* plan) {

@@ -120,6 +120,10 @@ def _plan(grids, prm, bufs=None, dt=0.1, autotune=0, out=True):
                                       ctypes.byref(h) if out else None, None)
 
 
+def L_mode_null():
+    return B.lib().batch_patches_launch_mode(None)
+
+
 def test_batch_plan_validation():
     g = I.cell_centred(8, -1, 1, 3)
     prm = B.Params().c()
@@ -128,7 +132,9 @@ def test_batch_plan_validation():
     assert _plan([g], prm, dt=float("inf")) == B.BSSN_EINVAL
     assert _plan([g], prm, autotune=2) == B.BSSN_EINVAL
     assert _plan([g], prm, autotune=B.BSSN_BATCH_TILE(5)) == B.BSSN_EINVAL
-    assert _plan([g], prm, autotune=0x200) == B.BSSN_EINVAL
+    assert _plan([g], prm, autotune=0x400) == B.BSSN_EINVAL
+    assert _plan([g], prm, autotune=0x201) == B.BSSN_EINVAL  # tile w/o 0x100
+    assert L_mode_null() == B.BSSN_EINVAL
     gp = I.cell_centred(8, -1, 1, 3, I.BC_PERIODIC)
     assert _plan([g, gp], prm) == B.BSSN_EINVAL
     assert "patch 1" in B.bssn_last_error()

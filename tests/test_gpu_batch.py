@@ -64,13 +64,19 @@ def results(grids, u):
 
 
 @pytest.mark.parametrize("order,precision,autotune", [
-    (4, 0, 1), (4, 1, 1), (4, 0, 0), (8, 0, 1), (8, 1, 0)])
+    (4, 0, 1), (4, 1, 1), (4, 0, 0), (8, 0, 1), (8, 1, 0),
+    (4, 0, 0x200), (4, 1, 0x301)])
 def test_batched_equals_per_patch_bitwise(B, order, precision, autotune):
     grids, us = host_set(9, 41 + order + precision, 17, 61, order)
     bufs = device_set(B, us)
     prm = B.Params(fd_order=order, precision=precision)
     dt = 0.25 * 0.125
     plan = B.batch_patches_plan(grids, prm, *bufs, dt, autotune=autotune)
+    mode = B.batch_patches_launch_mode(plan)
+    if autotune & B.BSSN_BATCH_PER_PATCH:
+        assert mode == B.BSSN_BATCH_PER_PATCH
+    elif autotune == 0:
+        assert mode == 0
     reset(bufs, us)  # autotuning ran stage 0 into a and acc
     B.batch_patches(plan, 2)
     got = results(grids, bufs[0])
