@@ -218,3 +218,31 @@ def test_forced_tiles_bitwise_and_oracle(B, tile, precision):
             err = np.abs(got[p] - o).reshape(25, -1).max(1)
             assert (err <= tol).all(), (p, err / np.maximum(tol, 1e-300))
     plan.destroy()
+
+
+@pytest.mark.parametrize("mode", [0, 0x200])
+def test_graph_replays_match_eager_every_step(B, mode):
+    """The step graph replayed one step at a time, with eager torch work and
+    synchronisations between replays, equals eager launches of the same
+    kernels after every step (persistent and per-patch launch modes)."""
+    grids, us = host_set(6, 303, 17, 45)
+    ga = device_set(B, us)
+    gb = device_set(B, us)
+    flags = B.BSSN_BATCH_TILE(0) | mode
+    graph = B.batch_patches_plan(grids, B.Params(), *ga, 0.03125,
+                                 autotune=flags)
+    eager = B.batch_patches_plan(grids, B.Params(), *gb, 0.03125,
+                                 autotune=flags)
+    assert B.batch_patches_launch_mode(graph) == mode
+    for step in range(4):
+        B.batch_patches(graph, 1)
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        float(junk.sum())            # eager work between replays
+        torch.cuda.synchronize()
+        B.batch_patches_unbatched(eager, 1)
+        x = results(grids, ga[0])
+        y = results(grids, gb[0])
+        for p in range(len(grids)):
+            assert np.array_equal(x[p], y[p]), (step, p)
+    graph.destroy()
+    eager.destroy()
