@@ -81,15 +81,20 @@ __device__ __forceinline__ void dma_offsets(const Patch& P, int x0, int y0,
   const int g = P.ghost;
 #pragma unroll
   for (int j = 0; j < Geo::L; ++j) {
-    int q = (wave * Geo::L + j) * 64 + lane;
-    if (q >= Geo::G) q = 0;  // padding lanes reload granule 0 into the pad
+    const int q = (wave * Geo::L + j) * 64 + lane;
     const int col = q % (Geo::W / 2);
     const int row = q / (Geo::W / 2);
     const int yy = row % Geo::H, zz = row / Geo::H;
     const int64_t e = int64_t(z0 + zz + g - Geo::R) * P.sz +
                       int64_t(y0 + yy + g - Geo::R) * P.sy +
                       (x0 + g - Geo::R - 1) + 2 * col;
-    off[j] = uint32_t(e * 8);  // < 0 wraps to a huge offset: reads 0
+    // Padding lanes (granules past the box) fill the buffer's pad with the
+    // zeros of an offset beyond the slot (slots are < 2^31 bytes), without
+    // traffic.  The one granule that can start 8 bytes before the slot
+    // (ghost = R, grid corner) has offset 2^32 - 8: its first element (the
+    // alignment column, never read) is out of range, and its second wraps
+    // to offset 0, the slot's first element, which it is.
+    off[j] = q < Geo::G ? uint32_t(e * 8) : 0x80000000u;
   }
 }
 
