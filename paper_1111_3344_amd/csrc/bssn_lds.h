@@ -136,14 +136,58 @@ __device__ __forceinline__ v4i slot_dma_rsrc(const double* u, int64_t sf,
   return dma_rsrc(b + s * sf, nbytes);
 }
 
+// Slots whose stencils include mixed second derivatives (gt_ij, phi,
+// alpha, beta^i); the others only read the three axis lines through each
+// point.
+__host__ __device__ constexpr bool needs_mixed(int slot) {
+  return (slot >= GXX && slot <= GZZ) || slot == PHI || slot == ALP ||
+         (slot >= BETX && slot <= BETZ);
+}
+
+// Per-lane mask of the box granules this lane's DMA instructions move that
+// a slot's stencils never read: bit j (star-only slots) or 16 + j (slots
+// with mixed derivatives) for instruction j.  Star stencils read whole
+// rows through the tile (y and z both in the tile), and the tile's x range
+// of rows with y or z in the tile; mixed derivatives also read every row
+// with y or z in the tile, and the tile's x range of the other rows.  The
+// mask depends only on the lane, not on the tile.
+template <class Geo>
+__device__ __forceinline__ uint32_t dma_skip_mask(int wave, int lane) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int j = 0; j < Geo::L; ++j) {
+    const int q = (wave * Geo::L + j) * 64 + lane;
+    const int col = q % (Geo::W / 2);
+    const int row = q / (Geo::W / 2);
+    const int yy = row % Geo::H, zz = row / Geo::H;
+    const bool in_y = yy >= Geo::R && yy < Geo::R + Geo::TY;
+    const bool in_z = zz >= Geo::R && zz < Geo::R + Geo::TZ;
+    // box column 0 is x0 - R - 1; the tile's x range is columns R+1 .. R+TX
+    const bool in_x = 2 * col + 1 >= Geo::R + 1 && 2 * col <= Geo::R + Geo::TX;
+    const bool star = (in_y && in_z) || ((in_y || in_z) && in_x);
+    const bool mix = in_y || in_z || in_x;
+    if (!star) m |= 1u << j;
+    if (!mix) m |= 1u << (16 + j);
+  }
+  return m;
+}
+
+// The DMA of slot `slot`'s box into buf; granules the slot never reads get
+// an offset beyond the slot (no traffic; their LDS words are not read).
 template <class Geo>
 __device__ __forceinline__ void dma_issue(const Patch& P, int slot,
                                           double* buf, int wave,
-                                          const uint32_t (&off)[Geo::L]) {
+                                          const uint32_t (&off)[Geo::L],
+                                          uint32_t skip) {
+  static_assert(Geo::L <= 16, "skip mask holds 16 instructions per kind");
   const v4i r = slot_dma_rsrc(P.u_s, P.sf, slot, int32_t(P.sf * 8));
   const uint32_t l0 = lds_addr(buf) + uint32_t(wave * Geo::L) * 1024u;
+  const int sh = needs_mixed(slot) ? 16 : 0;
 #pragma unroll
-  for (int j = 0; j < Geo::L; ++j) dma16(r, off[j], l0 + j * 1024u);
+  for (int j = 0; j < Geo::L; ++j) {
+    const uint32_t o = off[j] | ((skip << (31 - (sh + j))) & 0x80000000u);
+    dma16(r, o, l0 + j * 1024u);
+  }
 }
 
 // Centre values the algebra needs before the slot's own phase (gt_ij,
@@ -219,6 +263,7 @@ struct LdLds {
   int nxt[3];              // next tile's origin (centre block prefetch)
   int pbase;               // (k * NSLOT) mod NBUF
   int wave, lane, tid;
+  uint32_t skip;           // dma_skip_mask of this lane
   int cidx;                // element index in a box of the thread's centre
                            // or (CORNER) of its stencil corner
                            // (x-R, y-R, z-R)
@@ -283,11 +328,11 @@ struct LdLds {
     if (q < NSLOT) {
 #pragma unroll
       for (int j = 0; j < Geo::L; ++j) o[j] = off_cur[j];
-      dma_issue<Geo>(*P, kPhaseSlot[q], buffer(q), wave, o);
+      dma_issue<Geo>(*P, kPhaseSlot[q], buffer(q), wave, o, skip);
     } else {
 #pragma unroll
       for (int j = 0; j < Geo::L; ++j) o[j] = off_nxt[j];
-      dma_issue<Geo>(*P, kPhaseSlot[q - NSLOT], buffer(q), wave, o);
+      dma_issue<Geo>(*P, kPhaseSlot[q - NSLOT], buffer(q), wave, o, skip);
     }
     if (p == kCentrePhase)
       centre_dma(*P, sc, nxt[0], nxt[1], nxt[2], wave, lane);
@@ -401,11 +446,16 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     Wk.origin(ntile_mine > 1 ? 1 : 0, xn, yn, zn);
     dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
   }
+  // DMA trimmed to the granules each slot reads where measured faster (the
+  // out-of-range lanes still cost their address slot, and the mask costs a
+  // register the order-4 FP64 kernel does not have to spare)
+  constexpr bool trim = MIXED || ORDER == 8;
+  const uint32_t skip = trim ? dma_skip_mask<Geo>(wave, lane) : 0u;
   // prologue: centre block and phases 0 .. NBUF-2 of the first tile
   centre_dma(P, sc, x0, y0, z0, wave, lane);
 #pragma unroll
   for (int q = 0; q < Geo::NBUF - 1; ++q)
-    dma_issue<Geo>(P, kPhaseSlot[q], ring + q * Geo::BUFD, wave, offA);
+    dma_issue<Geo>(P, kPhaseSlot[q], ring + q * Geo::BUFD, wave, offA, skip);
 
   const int32_t nbytes = int32_t(P.sf * 8);
   const uint32_t sy8 = uint32_t(P.sy) * 8u, sz8 = uint32_t(P.sz) * 8u;
@@ -432,6 +482,7 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     ld.wave = wave;
     ld.lane = lane;
     ld.tid = tid;
+    ld.skip = skip;
     ld.stage = stage;
     ld.nbytes = nbytes;
     ld.epi_loads = early ? epilogue_loads(stage) : 0;
