@@ -1,6 +1,6 @@
 """Benchmark of the fused BSSN RHS + RK4 path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bl1-128]
 
 One "step" is one classical RK4 step (four fused stage launches) over the
 whole grid.  The timed region covers exactly K steps with inputs resident in
@@ -42,24 +42,24 @@ FP64_PEAK_TFLOPS = 78.6
 
 WORKLOADS = {
     # name: (n, lo, hi, ghost, masses, centres, order, dt, description)
-    "c1": (32, -1.6, 1.6, 3, None, None, 4, 0.025,
-           "c1: 32^3 + 3 ghosts periodic, Minkowski + 1e-8 noise, 4th order"),
-    "c2": (128, -8.0, 8.0, 3, (1.0,), ((0.0, 0.0, 0.0),), 4, 0.03125,
-           "c2: single Brill-Lindquist puncture M=1, 128^3 + 3 ghosts on "
+    "noise32": (32, -1.6, 1.6, 3, None, None, 4, 0.025,
+           "32^3 + 3 ghosts periodic, Minkowski + 1e-8 noise, 4th order"),
+    "bl1-128": (128, -8.0, 8.0, 3, (1.0,), ((0.0, 0.0, 0.0),), 4, 0.03125,
+           "single Brill-Lindquist puncture M=1, 128^3 + 3 ghosts on "
            "[-8,8]^3, static boundary, 4th-order FD, KO eps=0.1, RK4 "
            "dt=0.03125"),
-    "c3": (256, -16.0, 16.0, 3, (0.5, 0.5), ((3.0, 0, 0), (-3.0, 0, 0)), 4,
+    "bl2-256": (256, -16.0, 16.0, 3, (0.5, 0.5), ((3.0, 0, 0), (-3.0, 0, 0)), 4,
            0.03125,
-           "c3: two Brill-Lindquist punctures m=0.5 at (+-3,0,0), 256^3 + 3 "
+           "two Brill-Lindquist punctures m=0.5 at (+-3,0,0), 256^3 + 3 "
            "ghosts on [-16,16]^3, static boundary, 4th-order FD, RK4 "
            "dt=0.03125"),
-    "c4": (None, None, None, 3, None, None, 4, 0.03125,
-           "c4: 256 uneven static patches, interiors U{24..96} per axis, "
+    "patches256": (None, None, None, 3, None, None, 4, 0.03125,
+           "256 uneven static patches, interiors U{24..96} per axis, "
            "3 ghosts, h=0.125, one Brill-Lindquist puncture each (mass "
            "U[0.3,1.0], seeded centre), 4th order, RK4 dt=0.03125"),
-    "c5": (384, -24.0, 24.0, 5, (0.6, 0.4), ((4.0, 0, 0), (-4.0, 0, 0)), 8,
+    "bl2-384-o8": (384, -24.0, 24.0, 5, (0.6, 0.4), ((4.0, 0, 0), (-4.0, 0, 0)), 8,
            0.03125,
-           "c5: two Brill-Lindquist punctures m=0.6/0.4 at (+-4,0,0), 384^3 "
+           "two Brill-Lindquist punctures m=0.6/0.4 at (+-4,0,0), 384^3 "
            "+ 5 ghosts on [-24,24]^3, static boundary, 8th-order FD, RK4 "
            "dt=0.03125"),
 }
@@ -344,7 +344,8 @@ def batched(B, torch, steps, warmup, npatch=256):
     return out
 
 
-ACCURACY_STEPS = {"c1": 1, "c2": 100, "c3": 200, "c5": 50}
+ACCURACY_STEPS = {"noise32": 1, "bl1-128": 100, "bl2-256": 200,
+                  "bl2-384-o8": 50}
 
 
 def accuracy(B, torch, name, steps=None, r_exc=1.0):
@@ -406,7 +407,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=list(WORKLOADS))
+    ap.add_argument("--workload", default="bl1-128", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--path", default="auto", choices=["auto", "direct"],
@@ -435,9 +436,9 @@ def main():
 
     B.bssn_set_path(B.BSSN_PATH_DIRECT if args.path == "direct"
                     else B.BSSN_PATH_AUTO)
-    if args.workload == "c4":
+    if args.workload == "patches256":
         r = batched(B, torch, args.steps, args.warmup)
-        print(json.dumps({"workload": WORKLOADS["c4"][8], "steps": args.steps,
+        print(json.dumps({"workload": WORKLOADS["patches256"][8], "steps": args.steps,
                           "warmup": args.warmup, **r}), flush=True)
         return
     if args.accuracy:

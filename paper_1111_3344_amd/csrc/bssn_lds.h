@@ -427,7 +427,7 @@ __device__ __forceinline__ Walk walk_contig(int tlo, int n, int ntx,
 // below G.alpha_thr (then FP64); the branch is uniform over the workgroup.
 // On return every DMA of this call has landed; the caller places a barrier
 // before the ring is filled again.
-template <int ORDER, bool MIXED>
+template <int ORDER, bool MIXED, bool TRIM>
 __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
                                           const int stage, const Walk& Wk,
                                           double* ring, double* sc) {
@@ -446,11 +446,9 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     Wk.origin(ntile_mine > 1 ? 1 : 0, xn, yn, zn);
     dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
   }
-  // DMA trimmed to the granules each slot reads where measured faster (the
-  // out-of-range lanes still cost their address slot, and the mask costs a
-  // register the order-4 FP64 kernel does not have to spare)
-  constexpr bool trim = MIXED || ORDER == 8;
-  const uint32_t skip = trim ? dma_skip_mask<Geo>(wave, lane) : 0u;
+  // TRIM: DMA only the granules each slot reads (the out-of-range lanes
+  // still cost their address slot, and the mask costs a register)
+  const uint32_t skip = TRIM ? dma_skip_mask<Geo>(wave, lane) : 0u;
   // prologue: centre block and phases 0 .. NBUF-2 of the first tile
   centre_dma(P, sc, x0, y0, z0, wave, lane);
 #pragma unroll
@@ -577,7 +575,9 @@ __global__ void __launch_bounds__(256)
     walk_range(walk_pos(blockIdx.x, nwg), nwg, M.ntiles, tlo, thi);
     w = walk_contig(tlo, thi - tlo, M.ntx, M.ntz);
   }
-  lds_tiles<ORDER, MIXED>(P, G, stage, w, ring, sc);
+  // trimmed DMA where measured faster: not in the order-4 FP64 kernel,
+  // where the mask register costs a spill
+  lds_tiles<ORDER, MIXED, MIXED || ORDER == 8>(P, G, stage, w, ring, sc);
 }
 
 // Many patches: workgroup b runs the items [wstart[q], wstart[q+1]) for
@@ -597,7 +597,9 @@ __global__ void __launch_bounds__(256)
     const LdsItem it = items[i];
     const Patch P = patches[it.patch];
     const Walk w = walk_contig(it.tlo, it.thi - it.tlo, it.ntx, it.ntz);
-    lds_tiles<ORDER, MIXED>(P, G, stage, w, ring, sc);
+    // trimmed DMA always: many patches at once miss L2 more often, so the
+    // saved traffic matters more than the register
+    lds_tiles<ORDER, MIXED, true>(P, G, stage, w, ring, sc);
     __builtin_amdgcn_s_barrier();  // every wave is done with ring and sc
   }
 }

@@ -57,12 +57,12 @@ def test_summary_scales_by_the_copy_calibration(tmp_path, monkeypatch):
     # a summary stamped with other sources is not used
     prof = tmp_path / "profiles"
     prof.mkdir()
-    (prof / "traffic_k_x_c9.txt").write_text(
+    (prof / "traffic_k_x_w9.txt").write_text(
         text.replace(kv["source_sha256"], "0" * 16))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: kv["source_sha256"])
-    got, why = bench.profile_figures("c9", "k_x")
+    got, why = bench.profile_figures("w9", "k_x")
     assert got is None and "changed" in why
-    (prof / "traffic_k_x_c9.txt").write_text(text)
-    got, _ = bench.profile_figures("c9", "k_x")
+    (prof / "traffic_k_x_w9.txt").write_text(text)
+    got, _ = bench.profile_figures("w9", "k_x")
     assert got["write_kib_per_launch"] == "500"

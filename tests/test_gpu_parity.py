@@ -73,7 +73,7 @@ def state_tol(grid, u0, u1, nsteps):
 
 CASES = {
     # name: (grid, data, params kwargs)
-    "c1-noise-periodic-32": (
+    "noise-periodic-32": (
         lambda: I.cell_centred(32, -1.6, 1.6, 3, I.BC_PERIODIC),
         lambda g: I.minkowski_noise(g), {}),
     "smooth-static-ragged": (
@@ -153,7 +153,7 @@ def test_rhs_matches_oracle(B, case, path):
 
 
 @pytest.mark.parametrize("case,nsteps,dt", [
-    ("c1-noise-periodic-32", 1, 0.025),
+    ("noise-periodic-32", 1, 0.025),
     ("smooth-static-ragged", 2, 0.02),
     ("smooth-periodic", 2, 0.02),
     ("bl-two-punctures-48", 2, 0.1),
@@ -209,12 +209,12 @@ def test_runs_are_bitwise_reproducible(B, path):
 
 # ---- full-size configurations: sampled points ------------------------------
 FULL = {
-    "c2-128": (lambda: I.cell_centred(128, -8, 8, 3),
+    "bl1-128": (lambda: I.cell_centred(128, -8, 8, 3),
                lambda g: I.brill_lindquist(g, (1.0,), ((0, 0, 0),)), 4),
-    "c3-256": (lambda: I.cell_centred(256, -16, 16, 3),
+    "bl2-256": (lambda: I.cell_centred(256, -16, 16, 3),
                lambda g: I.brill_lindquist(g, (0.5, 0.5),
                                            ((3, 0, 0), (-3, 0, 0))), 4),
-    "c5-384-order8": (lambda: I.cell_centred(384, -24, 24, 5),
+    "bl2-384-order8": (lambda: I.cell_centred(384, -24, 24, 5),
                       lambda g: I.brill_lindquist(g, (0.6, 0.4),
                                                   ((4, 0, 0), (-4, 0, 0))),
                       8),
