@@ -10,19 +10,25 @@
 // buffer_load_dwordx4 ... lds (each lane moves one granule straight into
 // LDS, no registers), NBUF - 1 phases ahead of use, and the pipeline runs
 // on across tile boundaries, so the HBM/L2 latency of one phase hides behind
-// the arithmetic of the previous ones.  Stencil taps are then ds_read_b64
-// with immediate offsets from one per-thread address.
+// the arithmetic of the previous ones.  Stencil taps are then ds_read_b64 /
+// ds_read2_b64 with immediate offsets from one per-thread address.  Where
+// it measured faster, granules a slot's stencils never read are not
+// fetched (their lanes get an offset beyond the slot).
 //
-// Synchronisation per phase: wait until at most (NBUF-2)*L of this wave's
-// DMA instructions are outstanding (so the current phase's box has landed),
-// barrier (all waves' granules have landed, and every wave is done with the
-// previous phase's buffer), then issue the DMA for phase p + NBUF - 1 into
-// the buffer phase p - 1 used.  Buffers are distinct __shared__ arrays
-// selected by compile-time phase numbers.
+// Synchronisation per phase: wait until this wave's DMA for the phase has
+// landed (an explicit vmcnt: the number of memory instructions the wave
+// issued after it), barrier (all waves' granules have landed, and every
+// wave is done with the previous phase's buffer), then issue the DMA for
+// phase p + NBUF - 1 into the buffer phase p - 1 used.
 //
-// Tiles are walked persistently: workgroup b takes tiles in an order that
-// keeps the tiles in flight on one XCD (b mod 8) contiguous in x, so halos
-// shared by x-neighbours are hits in that XCD's L2.
+// The epilogue (acc and the stage output) uses non-temporal buffer stores;
+// in the order-4 FP64 kernel its loads are issued three phases before the
+// end of the point function.
+//
+// Tiles are walked persistently (Walk): in blocks of 32 tiles per XCD
+// stepping together in z where the tile grid allows, else in contiguous
+// z-column runs, so tiles whose halos overlap are in flight on one XCD and
+// meet in its L2.
 #pragma once
 #include <hip/hip_runtime.h>
 
