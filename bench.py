@@ -156,13 +156,28 @@ KERNEL_SOURCES = ("bssn_internal.h", "bssn_point.h", "bssn_stage.h",
 CALIB_BYTES = 1 << 30
 
 
-def kernel_source_hash():
+def strip_comments(src):
+    """C/C++ source without comments and with whitespace runs collapsed, so
+    that only code changes change the hash (no string in these sources
+    contains a comment marker)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
+def kernel_source_hash(sources=None):
+    """Hash of the kernel sources' code (comments and layout ignored)."""
     import hashlib
     hsh = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1111_3344_amd", "csrc")
     for f in KERNEL_SOURCES:
-        with open(os.path.join(d, f), "rb") as fh:
-            hsh.update(fh.read())
+        if sources is not None:
+            text = sources[f]
+        else:
+            with open(os.path.join(d, f)) as fh:
+                text = fh.read()
+        hsh.update(strip_comments(text).encode())
     return hsh.hexdigest()[:16]
 
 

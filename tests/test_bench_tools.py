@@ -66,3 +66,18 @@ def test_summary_scales_by_the_copy_calibration(tmp_path, monkeypatch):
     (prof / "traffic_k_x_w9.txt").write_text(text)
     got, _ = bench.profile_figures("w9", "k_x")
     assert got["write_kib_per_launch"] == "500"
+
+
+def test_source_hash_ignores_comments_not_code():
+    src = {f: open(os.path.join(ROOT, "paper_1111_3344_amd", "csrc", f)).read()
+           for f in bench.KERNEL_SOURCES}
+    h0 = bench.kernel_source_hash(src)
+    assert h0 == bench.kernel_source_hash()
+    f = bench.KERNEL_SOURCES[-1]
+    commented = dict(src)
+    commented[f] = "// a new comment\n/* and a block\n comment */\n" + \
+        src[f].replace("\n", "\n  ", 3)
+    assert bench.kernel_source_hash(commented) == h0
+    changed = dict(src)
+    changed[f] = src[f] + "\nint extra_symbol = 1;\n"
+    assert bench.kernel_source_hash(changed) != h0
