@@ -63,6 +63,17 @@ struct TileGeo<8> {
   static constexpr bool EARLY_EPI = false;  // no registers to hold them
 };
 
+// The same box geometry with a ring of NB buffers.
+template <class Base, int NB>
+struct GeoRing : Base {
+  static constexpr int NBUF = NB;
+};
+// FP32 tiles of the split mixed stage: at order 4 a ring of 3 boxes keeps
+// the workgroup within 80 KB of LDS, so two of them share a CU (the FP32
+// point function fits the 256 registers that takes; the FP64 one does not).
+template <int ORDER>
+using GeoF32 = GeoRing<TileGeo<ORDER>, 3>;
+
 static_assert(TileGeo<4>::TX == kLdsTile[0] && TileGeo<4>::TY == kLdsTile[1] &&
                   TileGeo<4>::TZ == kLdsTile[2] &&
                   TileGeo<8>::TX == kLdsTile[0] &&
@@ -382,6 +393,15 @@ __host__ __device__ __forceinline__ void walk_range(int lin, int nwg,
   hi = int((int64_t(ntiles) * (lin + 1)) / nwg);
 }
 
+// Origin (interior coordinates) of tile t of the TileMap numbering.
+__device__ __forceinline__ void tile_origin(int t, int ntx, int ntz, int& x0,
+                                            int& y0, int& z0) {
+  const int iz = t % ntz, col = t / ntz;
+  x0 = (col % ntx) * kLdsTile[0];
+  y0 = (col / ntx) * kLdsTile[1];
+  z0 = iz * kLdsTile[2];
+}
+
 // The tiles one workgroup visits, in order (one walker type, so the
 // right-hand side is inlined once).  Tile k is c = k / nk, kz = k mod nk:
 //   contiguous walk (bx = 0): tiles tlo + k of the TileMap numbering
@@ -403,11 +423,7 @@ struct Walk {
   __device__ __forceinline__ void origin(int k, int& x0, int& y0,
                                          int& z0) const {
     if (bx == 0) {
-      const int t = tlo + k;
-      const int iz = t % ntz, col = t / ntz;
-      x0 = (col % ntx) * kLdsTile[0];
-      y0 = (col / ntx) * kLdsTile[1];
-      z0 = iz * kLdsTile[2];
+      tile_origin(tlo + k, ntx, ntz, x0, y0, z0);
     } else {
       const int r = xcd + 8 * (k / nk), kz = k % nk;
       x0 = ((r % nrx) * bx + lx) * kLdsTile[0];
@@ -427,17 +443,61 @@ __device__ __forceinline__ Walk walk_contig(int tlo, int n, int ntx,
   return w;
 }
 
-// Tiles [tlo, thi) of patch P (numbered as in TileMap), pipelined through
-// the workgroup's LDS ring.  MIXED = false: FP64 everywhere.  MIXED = true:
-// per tile, FP32 stencils and algebra unless the tile's minimum lapse is
-// below G.alpha_thr (then FP64); the branch is uniform over the workgroup.
+// Arithmetic of the tiles of an LDS kernel:
+//   TP_F64   FP64 everywhere;
+//   TP_MIXED per tile, FP32 stencils and algebra unless the tile's minimum
+//            lapse is below G.alpha_thr, then FP64 (both in one kernel);
+//   TP_F32   the FP32 tiles of that split only: a tile that needs FP64 runs
+//            through the pipeline without arithmetic and is left to
+//            k_stage_lds_f64tiles, which finds it by the same test.
+enum : int { TP_F64 = 0, TP_MIXED = 1, TP_F32 = 2 };
+
+// Minimum lapse over the tile's points, taken from the centre block (which
+// holds all 256 of them) in every wave, so that each wave reaches the same
+// value without a barrier.  Points outside the grid do not count.  fmin is
+// exact, so the value does not depend on the order of reduction;
+// k_stage_lds_f64tiles computes the same minimum from global memory.
+__device__ __forceinline__ double tile_lapse_min(const double* sc,
+                                                 const Patch& P, int x, int y,
+                                                 int z0, int lane) {
+  const lds_double* sa = (const lds_double*)sc + centre_index(ALP) * 256;
+  double a = 1.0e300;
+  const bool in_xy = x < P.n[0] && y < P.n[1];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const double v = sa[w * 64 + lane];
+    if (in_xy && z0 + w < P.n[2]) a = fmin(a, v);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a = fmin(a, __shfl_xor(a, off, 64));
+  return a;
+}
+
+// The point function and epilogue of one thread's point in arithmetic T.
+template <int ORDER, typename T, bool EARLY, class LD>
+__device__ __forceinline__ void tile_point(const LD& ld, const Patch& P,
+                                           const Gauge& G, int stage,
+                                           double xc, double yc, double zc,
+                                           uint32_t vc, int32_t nbytes,
+                                           bool active) {
+  T r[NSLOT];
+  point_rhs<ORDER, T>(ld, P, xc, yc, zc, G, r);
+  if (EARLY) {
+    if (active) epilogue_store<T>(P, stage, r, vc, nbytes, ld.un, ld.ac);
+  } else {
+    epilogue_all<T>(P, stage, r, ld.vc_epi, nbytes, active);
+  }
+}
+
+// The tiles Wk names, of patch P, pipelined through the workgroup's LDS
+// ring (Geo: box and ring geometry; WK: a walk with count() and origin()).
 // On return every DMA of this call has landed; the caller places a barrier
 // before the ring is filled again.
-template <int ORDER, bool MIXED, bool TRIM>
+template <int ORDER, int TP, bool TRIM, class Geo = TileGeo<ORDER>,
+          class WK = Walk>
 __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
-                                          const int stage, const Walk& Wk,
+                                          const int stage, const WK& Wk,
                                           double* ring, double* sc) {
-  using Geo = TileGeo<ORDER>;
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -471,8 +531,8 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     const int g = P.ghost;
     // early epilogue loads where the registers allow (order 4, FP64);
     // corner-based tap addressing for the mixed and order-8 kernels
-    constexpr bool early = Geo::EARLY_EPI && !MIXED;
-    constexpr bool corner = MIXED || ORDER == 8;
+    constexpr bool early = Geo::EARLY_EPI && TP == TP_F64;
+    constexpr bool corner = TP != TP_F64 || ORDER == 8;
     LdLds<Geo, early, corner> ld;
     ld.P = &P;
     ld.ring = ring;
@@ -503,40 +563,30 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     const double xc = P.origin[0] + x * P.h[0];
     const double yc = P.origin[1] + y * P.h[1];
     const double zc = P.origin[2] + z * P.h[2];
-    bool f64 = true;
-    if constexpr (MIXED) {
-      __shared__ double wmin[4];
-      double a = active ? ld.g(ALP) : 1.0e300;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1)
-        a = fmin(a, __shfl_xor(a, off, 64));
-      if (lane == 0) wmin[wave] = a;
-      __builtin_amdgcn_s_barrier();
-      const double m = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
-      f64 = m < G.alpha_thr;
-      __builtin_amdgcn_s_barrier();  // wmin is reused by the next tile
-    }
-    if (f64) {
-      double r[NSLOT];
-      point_rhs<ORDER, double>(ld, P, xc, yc, zc, G, r);
-      if (early) {
-        if (active)
-          epilogue_store<double>(P, stage, r, vc, nbytes, ld.un, ld.ac);
-      } else {
-        epilogue_all<double>(P, stage, r, ld.vc_epi, nbytes, active);
-      }
+    bool computed = true;
+    if constexpr (TP == TP_F64) {
+      tile_point<ORDER, double, early>(ld, P, G, stage, xc, yc, zc, vc,
+                                       nbytes, active);
     } else {
-      float r[NSLOT];
-      point_rhs<ORDER, float>(ld, P, xc, yc, zc, G, r);
-      if (early) {
-        if (active)
-          epilogue_store<float>(P, stage, r, vc, nbytes, ld.un, ld.ac);
+      if (tile_lapse_min(sc, P, x, y, z0, lane) < G.alpha_thr) {
+        if constexpr (TP == TP_F32) {
+          // left to the FP64 pass: keep the pipeline going (waits,
+          // barriers, prefetches) through the tile's other phases
+#pragma unroll
+          for (int p = 1; p < NSLOT; ++p) ld.phase(p);
+          computed = false;
+        } else {
+          tile_point<ORDER, double, early>(ld, P, G, stage, xc, yc, zc, vc,
+                                           nbytes, active);
+        }
       } else {
-        epilogue_all<float>(P, stage, r, ld.vc_epi, nbytes, active);
+        tile_point<ORDER, float, early>(ld, P, G, stage, xc, yc, zc, vc,
+                                        nbytes, active);
       }
     }
-    prev_loads = early ? ld.epi_loads : epilogue_loads(stage);
-    prev_stores = __builtin_amdgcn_ballot_w64(active) != 0
+    prev_loads =
+        !computed ? 0 : (early ? ld.epi_loads : epilogue_loads(stage));
+    prev_stores = computed && __builtin_amdgcn_ballot_w64(active) != 0
                       ? epilogue_stores(stage)
                       : 0;
     // next tile: its offsets become current, prepare the one after
@@ -553,17 +603,10 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
 }
 
 // One patch: workgroup b takes the tiles of position walk_pos(b).
-template <int ORDER, bool MIXED>
-__global__ void __launch_bounds__(256)
-    k_stage_lds(const Patch P, const Gauge G, const int stage,
-                const TileMap M) {
-  using Geo = TileGeo<ORDER>;
-  __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
-  __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
-  const int nwg = gridDim.x;
-  Walk w;
+// The walk of workgroup blockIdx.x of a launch of nwg workgroups over M.
+__device__ __forceinline__ Walk walk_of(const TileMap& M, int nwg) {
+  Walk w{};
   if (M.bx > 0) {
-    w = Walk{};
     w.xcd = blockIdx.x & 7;
     const int l = blockIdx.x >> 3;
     w.lx = l % M.bx;
@@ -581,14 +624,124 @@ __global__ void __launch_bounds__(256)
     walk_range(walk_pos(blockIdx.x, nwg), nwg, M.ntiles, tlo, thi);
     w = walk_contig(tlo, thi - tlo, M.ntx, M.ntz);
   }
-  // trimmed DMA where measured faster: not in the order-4 FP64 kernel,
-  // where the mask register costs a spill
-  lds_tiles<ORDER, MIXED, MIXED || ORDER == 8>(P, G, stage, w, ring, sc);
+  return w;
+}
+
+// One patch, FP64: workgroup b takes the tiles of walk_of(b).
+template <int ORDER>
+__global__ void __launch_bounds__(256)
+    k_stage_lds(const Patch P, const Gauge G, const int stage,
+                const TileMap M) {
+  using Geo = TileGeo<ORDER>;
+  __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
+  __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  // trimmed DMA where measured faster: not at order 4, where the mask
+  // register costs a spill
+  lds_tiles<ORDER, TP_F64, ORDER == 8>(P, G, stage, walk_of(M, gridDim.x),
+                                       ring, sc);
+}
+
+// One patch, mixed precision, first launch: the FP32 tiles.  At order 4
+// two workgroups share a CU (GeoF32 ring, at most 256 registers per lane).
+template <int ORDER>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(ORDER == 4 ? 2 : 1,
+                                       ORDER == 4 ? 2 : 1)))
+    k_stage_lds_f32(const Patch P, const Gauge G, const int stage,
+                    const TileMap M) {
+  using Geo = GeoF32<ORDER>;
+  __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
+  __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  lds_tiles<ORDER, TP_F32, true, Geo>(P, G, stage, walk_of(M, gridDim.x),
+                                      ring, sc);
+}
+
+// Tiles named by an LDS list of tile numbers (TileMap numbering).
+typedef __attribute__((address_space(3))) int lds_int;
+struct ListWalk {
+  const lds_int* t;
+  int n, ntx, ntz;
+  __device__ __forceinline__ int count() const { return n; }
+  __device__ __forceinline__ void origin(int k, int& x0, int& y0,
+                                         int& z0) const {
+    tile_origin(t[k], ntx, ntz, x0, y0, z0);
+  }
+};
+
+// One patch, mixed precision, second launch: the FP64 tiles.  Workgroup b
+// examines the tiles t = (i * perm) mod ntiles for i in its share of an
+// even split of 0 .. ntiles - 1.  perm is coprime to ntiles, so every tile
+// is examined exactly once, and the tiles around a puncture (neighbours in
+// the numbering) land on many workgroups.  Per chunk of kF64Chunk tiles it
+// takes each tile's minimum lapse over its points from global memory (the
+// value tile_lapse_min finds in the FP32 launch, since fmin is exact), then
+// runs the tiles below the threshold through the FP64 pipeline.
+constexpr int kF64Chunk = 64;
+template <int ORDER>
+__global__ void __launch_bounds__(256)
+    k_stage_lds_f64tiles(const Patch P, const Gauge G, const int stage,
+                         const TileMap M, const int perm) {
+  using Geo = TileGeo<ORDER>;
+  __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
+  __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  __shared__ double wmin[4][kF64Chunk];
+  __shared__ int list[kF64Chunk];
+  __shared__ int nlist;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tx = lane & 15, ty = lane >> 4;
+  const int g = P.ghost;
+  const double* alp = P.u_s + int64_t(ALP) * P.sf;
+  int lo, hi;
+  walk_range(blockIdx.x, gridDim.x, M.ntiles, lo, hi);
+  for (int c0 = lo; c0 < hi; c0 += kF64Chunk) {
+    const int nc = hi - c0 < kF64Chunk ? hi - c0 : kF64Chunk;
+    // wave w reduces plane w of every tile of the chunk, 8 loads in flight
+    for (int c1 = 0; c1 < nc; c1 += 8) {
+      double a[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        a[c] = 1.0e300;
+        if (c1 + c < nc) {
+          int x0, y0, z0;
+          tile_origin(int((int64_t(c0 + c1 + c) * perm) % M.ntiles), M.ntx,
+                      M.ntz, x0, y0, z0);
+          const int x = x0 + tx, y = y0 + ty, z = z0 + wave;
+          if (x < P.n[0] && y < P.n[1] && z < P.n[2])
+            a[c] = alp[int64_t(z + g) * P.sz + int64_t(y + g) * P.sy + x + g];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+          a[c] = fmin(a[c], __shfl_xor(a[c], off, 64));
+        if (lane == 0 && c1 + c < nc) wmin[wave][c1 + c] = a[c];
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int n = 0;
+      for (int c = 0; c < nc; ++c) {
+        const double m =
+            fmin(fmin(wmin[0][c], wmin[1][c]), fmin(wmin[2][c], wmin[3][c]));
+        if (m < G.alpha_thr)
+          list[n++] = int((int64_t(c0 + c) * perm) % M.ntiles);
+      }
+      nlist = n;
+    }
+    __syncthreads();
+    const int n = nlist;
+    if (n > 0) {
+      const ListWalk w{(const lds_int*)list, n, M.ntx, M.ntz};
+      lds_tiles<ORDER, TP_F64, ORDER == 8>(P, G, stage, w, ring, sc);
+    }
+    __syncthreads();  // ring, sc, wmin and list are reused
+  }
 }
 
 // Many patches: workgroup b runs the items [wstart[q], wstart[q+1]) for
-// q = walk_pos(b).
-template <int ORDER, bool MIXED>
+// q = walk_pos(b).  TP is TP_F64 or TP_MIXED.
+template <int ORDER, int TP>
 __global__ void __launch_bounds__(256)
     k_stage_lds_batch(const Patch* __restrict__ patches,
                       const LdsItem* __restrict__ items,
@@ -605,7 +758,7 @@ __global__ void __launch_bounds__(256)
     const Walk w = walk_contig(it.tlo, it.thi - it.tlo, it.ntx, it.ntz);
     // trimmed DMA always: many patches at once miss L2 more often, so the
     // saved traffic matters more than the register
-    lds_tiles<ORDER, MIXED, true>(P, G, stage, w, ring, sc);
+    lds_tiles<ORDER, TP, true>(P, G, stage, w, ring, sc);
     __builtin_amdgcn_s_barrier();  // every wave is done with ring and sc
   }
 }
@@ -655,18 +808,48 @@ inline bool lds_path_ok(const Patch& P) {
 
 namespace bssn {
 
+// A multiplier coprime to n near n times the golden ratio's fraction:
+// i -> (i * perm) mod n is then a permutation of 0 .. n - 1 that scatters
+// neighbours.
+inline int tile_perm(int n) {
+  if (n <= 1) return 1;
+  int64_t p = int64_t(double(n) * 0.6180339887498949);
+  if (p < 1) p = 1;
+  for (;; ++p) {
+    int64_t a = p, b = n;
+    while (b) {
+      const int64_t r = a % b;
+      a = b;
+      b = r;
+    }
+    if (a == 1) return int(p % n == 0 ? 1 : p);
+  }
+}
+
+// precision 0: one FP64 launch.  Mixed: the FP32 tiles (two workgroups per
+// CU at order 4), then the FP64 tiles; both launches take the same per-tile
+// decision from the stage input, so each tile is written exactly once.
 template <int ORDER>
 hipError_t launch_stage_lds(const Patch& P, const Gauge& G, int stage,
                             int precision, int nwg_max, hipStream_t st) {
   TileMap M = lds_tile_map<ORDER>(P);
   const int nwg = M.ntiles < nwg_max ? M.ntiles : nwg_max;
-  choose_blocks(M, nwg);
-  if (precision == 0)
-    hipLaunchKernelGGL((k_stage_lds<ORDER, false>), dim3(nwg), dim3(256), 0,
-                       st, P, G, stage, M);
-  else
-    hipLaunchKernelGGL((k_stage_lds<ORDER, true>), dim3(nwg), dim3(256), 0,
-                       st, P, G, stage, M);
+  if (precision == 0) {
+    choose_blocks(M, nwg);
+    hipLaunchKernelGGL((k_stage_lds<ORDER>), dim3(nwg), dim3(256), 0, st, P,
+                       G, stage, M);
+    return hipGetLastError();
+  }
+  const int per_cu = ORDER == 4 ? 2 : 1;
+  const int nwg32 = M.ntiles < per_cu * nwg_max ? M.ntiles : per_cu * nwg_max;
+  TileMap M32 = M;
+  choose_blocks(M32, nwg32);
+  hipLaunchKernelGGL((k_stage_lds_f32<ORDER>), dim3(nwg32), dim3(256), 0, st,
+                     P, G, stage, M32);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_stage_lds_f64tiles<ORDER>), dim3(nwg), dim3(256), 0,
+                     st, P, G, stage, M, tile_perm(M.ntiles));
   return hipGetLastError();
 }
 
@@ -709,10 +892,10 @@ hipError_t launch_batch_t(const BatchLaunch& B, const Gauge& G, int stage,
   if (B.variant == VAR_LDS) {
     const LdsItem* it = static_cast<const LdsItem*>(B.items);
     if (precision == 0)
-      hipLaunchKernelGGL((k_stage_lds_batch<ORDER, false>), dim3(B.nwg),
+      hipLaunchKernelGGL((k_stage_lds_batch<ORDER, TP_F64>), dim3(B.nwg),
                          dim3(256), 0, st, B.patches, it, B.wstart, G, stage);
     else
-      hipLaunchKernelGGL((k_stage_lds_batch<ORDER, true>), dim3(B.nwg),
+      hipLaunchKernelGGL((k_stage_lds_batch<ORDER, TP_MIXED>), dim3(B.nwg),
                          dim3(256), 0, st, B.patches, it, B.wstart, G, stage);
     return hipGetLastError();
   }

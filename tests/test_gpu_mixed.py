@@ -139,3 +139,74 @@ def test_mixed_constraints_within_2x_of_fp64(B):
     assert nmx[0] <= 2 * n64[0] and nmx[2] <= 2 * n64[2]
     assert nmx[1] <= 2 * n64[1] and nmx[3] <= 2 * n64[3]
     assert mx.max() < 1e-3
+
+
+# The mixed stage runs in two launches: the FP32 tiles, then the tiles whose
+# minimum lapse is below the threshold in FP64.  Each tile must come out of
+# the launch its own minimum lapse chooses: FP64 tiles bitwise equal to the
+# FP64 method, FP32 tiles within the mixed tolerance of it (and not equal).
+# The smooth cases put the threshold near the median tile minimum, so that
+# FP64 tiles are scattered over the grid and over many chunks of the FP64
+# launch.
+SPLIT_CASES = {
+    "bl-two-punctures-64": (
+        lambda: I.cell_centred(64, -4, 4, 3),
+        lambda g: I.brill_lindquist(g, (0.5, 0.5),
+                                    ((1.5, 0, 0), (-1.5, 0, 0))), 4, 0.3),
+    "smooth-ragged-half": (
+        lambda: I.GridSpec((70, 38, 29), 3, (0.11, 0.13, 0.12),
+                           (-3.8, -2.4, -1.7), I.BC_STATIC),
+        lambda g: I.smooth_random(g, seed=7), 4, 0.886),
+    "smooth-one-tile": (
+        lambda: I.GridSpec((10, 3, 2), 3, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0),
+                           I.BC_STATIC),
+        lambda g: I.smooth_random(g, seed=3), 4, 2.0),
+    "order8-smooth-half": (
+        lambda: I.GridSpec((40, 22, 13), 5, (0.1, 0.12, 0.11),
+                           (-2.0, -1.3, -0.7), I.BC_STATIC),
+        lambda g: I.smooth_random(g, seed=5), 8, 0.855),
+}
+
+
+def _tile_min(a, tile=(4, 4, 16)):
+    """Per-tile minimum of an interior (z, y, x) array, tiles of 16 x 4 x 4
+    points (ragged at the far ends)."""
+    nz, ny, nx = a.shape
+    tz, ty, tx = tile
+    pz, py, px = -nz % tz, -ny % ty, -nx % tx
+    p = np.pad(a, ((0, pz), (0, py), (0, px)), constant_values=np.inf)
+    Z, Y, X = p.shape
+    return p.reshape(Z // tz, tz, Y // ty, ty, X // tx, tx).min(axis=(1, 3, 5))
+
+
+@pytest.mark.parametrize("case", list(SPLIT_CASES))
+def test_split_tiles_take_their_precision(B, case):
+    gfn, dfn, order, thr = SPLIT_CASES[case]
+    g = gfn()
+    u = dfn(g)
+    du = B.to_device(u)
+    outs = []
+    for prm in (B.Params(fd_order=order),
+                B.Params(fd_order=order, precision=1,
+                         fp64_alpha_threshold=thr)):
+        out = torch.zeros_like(du)
+        B.bssn_rhs(g, prm, du, out)
+        torch.cuda.synchronize()
+        outs.append(g.interior(out.cpu().numpy()))
+    r64, rmx = outs
+    flag = _tile_min(g.interior(u)[I.ALP]) < thr
+    nz, ny, nx = r64.shape[1:]
+    fp64_pt = np.repeat(np.repeat(np.repeat(flag, 4, 0), 4, 1), 16, 2)
+    fp64_pt = fp64_pt[:nz, :ny, :nx]
+    n64, nt = int(flag.sum()), flag.size
+    print(f"[split] {case}: {n64} of {nt} tiles FP64", flush=True)
+    if n64:
+        assert np.array_equal(rmx[:, fp64_pt], r64[:, fp64_pt])
+    if n64 < nt:
+        a, b = rmx[:, ~fp64_pt], r64[:, ~fp64_pt]
+        assert not np.array_equal(a, b)
+        D = np.abs(r64).reshape(25, -1).max(1)
+        D = np.where(D > 0, D, D.max())
+        assert np.all(np.abs(a - b).max(1) / D <= MIXED_RHS_TOL)
+    if case != "smooth-one-tile":
+        assert 0 < n64 < nt
