@@ -11,6 +11,9 @@
 //            whole patches are assigned to XCDs (balanced by tile count) and
 //            each patch's tiles are split evenly over the workgroups of its
 //            XCD, one item (patch, first tile, end tile) per workgroup;
+//            in mixed precision two workgroups per compute unit share each
+//            item's tiles (FP32 tiles), then an FP64 pass examines every
+//            tile of the list's patches (candidate list in scattered order);
 //   VAR_D*   one item per direct-kernel workgroup (patch, x0, y0, z0): a
 //            64 x 4 or 32 x 8 tile of one plane or of a 4-plane z-block.
 // The four stages of an RK4 step (one launch per variant in use per stage)
@@ -54,6 +57,7 @@ struct HostGroup {
   std::vector<LdsItem> lds;         // VAR_LDS items
   std::vector<int32_t> wstart;      // VAR_LDS, nwg + 1
   std::vector<DirectItem> direct;   // VAR_D*
+  std::vector<TileRef> cand;        // VAR_LDS, mixed: FP64-pass candidates
   size_t item_bytes() const {
     return variant == VAR_LDS ? lds.size() * sizeof(LdsItem)
                               : direct.size() * sizeof(DirectItem);
@@ -63,12 +67,45 @@ struct HostGroup {
   }
 };
 
+// Every LDS tile of the patches pids once, in the scattering order
+// i -> (i * tile_perm(T)) mod T of their joint numbering (patches in list
+// order, tiles in TileMap order), so that an even split of the list puts
+// the tiles around a puncture on many workgroups of the FP64 pass.
+int build_candidates(const std::vector<bssn_grid>& grids,
+                     const std::vector<int>& pids, HostGroup& G) {
+  std::vector<int64_t> base(pids.size() + 1, 0);
+  for (size_t i = 0; i < pids.size(); ++i) {
+    int ntx, nty, ntz;
+    lds_tiles_of(grids[pids[i]], ntx, nty, ntz);
+    base[i + 1] = base[i] + int64_t(ntx) * nty * ntz;
+  }
+  const int64_t T = base.back();
+  if (T >= (int64_t(1) << 31))
+    return fail(BSSN_EUNSUPPORTED, "batch: %lld LDS tiles exceed the "
+                "candidate list range", (long long)T);
+  const int64_t perm = tile_perm(T);
+  G.cand.resize(size_t(T));
+  for (int64_t i = 0; i < T; ++i) {
+    const int64_t t = (i * perm) % T;
+    const size_t j =
+        size_t(std::upper_bound(base.begin(), base.end(), t) - base.begin()) -
+        1;
+    G.cand[size_t(i)] = TileRef{pids[j], int32_t(t - base[j])};
+  }
+  return BSSN_OK;
+}
+
+// mixed: also the FP64-pass candidates of a VAR_LDS group.
 int build_group(const std::vector<bssn_grid>& grids,
                 const std::vector<int>& pids, int variant, int nwg_max,
-                HostGroup& G) {
+                bool mixed, HostGroup& G) {
   G = HostGroup();
   G.variant = variant;
   if (variant == VAR_LDS) {
+    if (mixed) {
+      const int rc = build_candidates(grids, pids, G);
+      if (rc) return rc;
+    }
     // XCD-affine: workgroup b runs on XCD b mod 8 and takes the item list
     // of position q = walk_pos(b), so positions [x*W, (x+1)*W) (W = nwg/8)
     // are the workgroups of XCD x.  Whole patches go to XCDs by a
@@ -176,8 +213,11 @@ int build_group(const std::vector<bssn_grid>& grids,
 size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 
 // Device copy of a group's work list (items, then wstart) at dst.
+// Device copy of a group's work list (items, wstart, then the candidates)
+// at dst.
 size_t group_bytes(const HostGroup& G) {
-  return align256(G.item_bytes()) + align256(G.wstart.size() * 4);
+  return align256(G.item_bytes()) + align256(G.wstart.size() * 4) +
+         align256(G.cand.size() * sizeof(TileRef));
 }
 hipError_t upload_group(const HostGroup& G, char* dst, BatchLaunch& L) {
   L.variant = G.variant;
@@ -185,13 +225,21 @@ hipError_t upload_group(const HostGroup& G, char* dst, BatchLaunch& L) {
   L.nitems = G.nitems();
   L.nwg = G.nwg;
   L.wstart = nullptr;
+  L.cand = nullptr;
+  L.ncand = 0;
   const void* src = G.variant == VAR_LDS ? (const void*)G.lds.data()
                                          : (const void*)G.direct.data();
   hipError_t e = hipMemcpy(dst, src, G.item_bytes(), hipMemcpyHostToDevice);
   if (e != hipSuccess || G.variant != VAR_LDS) return e;
   char* w = dst + align256(G.item_bytes());
   L.wstart = reinterpret_cast<const int32_t*>(w);
-  return hipMemcpy(w, G.wstart.data(), G.wstart.size() * 4,
+  e = hipMemcpy(w, G.wstart.data(), G.wstart.size() * 4,
+                hipMemcpyHostToDevice);
+  if (e != hipSuccess || G.cand.empty()) return e;
+  char* c = w + align256(G.wstart.size() * 4);
+  L.cand = reinterpret_cast<const TileRef*>(c);
+  L.ncand = int(G.cand.size());
+  return hipMemcpy(c, G.cand.data(), G.cand.size() * sizeof(TileRef),
                    hipMemcpyHostToDevice);
 }
 
@@ -366,7 +414,8 @@ int record_graph(bssn_batch_plan* P, int autotune, hipStream_t st) {
 float time_variant(bssn_batch_plan* P, const std::vector<int>& pids, int v,
                    hipStream_t st, int* rc) {
   HostGroup H;
-  if ((*rc = build_group(P->grids, pids, v, persistent_groups(), H)))
+  if ((*rc = build_group(P->grids, pids, v, persistent_groups(),
+                         P->precision != 0, H)))
     return -1.f;
   char* d = nullptr;
   hipError_t e = hipMalloc((void**)&d, group_bytes(H));
@@ -473,7 +522,8 @@ int plan_build(bssn_batch_plan* P, int autotune, hipStream_t st) {
       if (c.variant == v) pids.insert(pids.end(), c.pids.begin(), c.pids.end());
     if (pids.empty()) continue;
     groups.emplace_back();
-    int rc = build_group(P->grids, pids, v, persistent_groups(), groups.back());
+    int rc = build_group(P->grids, pids, v, persistent_groups(),
+                         P->precision != 0, groups.back());
     if (rc) return rc;
   }
   size_t total = pbytes;

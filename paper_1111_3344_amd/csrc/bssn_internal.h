@@ -55,6 +55,28 @@ struct LdsItem {
 struct DirectItem {
   int32_t patch, x0, y0, z0;  // planes z0 .. z0 + depth - 1
 };
+// One LDS tile of one patch (the FP64 pass of mixed precision).
+struct TileRef {
+  int32_t patch, tile;
+};
+
+// A multiplier coprime to n near n times the golden ratio's fraction, so
+// that i -> (i * perm) mod n is a permutation of 0 .. n - 1 that scatters
+// neighbours (the tiles around a puncture) far apart.
+inline int64_t tile_perm(int64_t n) {
+  if (n <= 1) return 1;
+  int64_t p = int64_t(double(n) * 0.6180339887498949);
+  if (p < 1) p = 1;
+  for (;; ++p) {
+    int64_t a = p, b = n;
+    while (b) {
+      const int64_t r = a % b;
+      a = b;
+      b = r;
+    }
+    if (a == 1) return p;
+  }
+}
 
 // Kernel variants a batch plan chooses between, per patch size class:
 // the LDS-pipelined persistent kernel (16 x 4 x 4 tiles) and the direct-load

@@ -42,7 +42,8 @@ bool variant_ok_o4(const Patch& P, int variant);
 bool variant_ok_o8(const Patch& P, int variant);
 
 // One batched launch over device work lists.  VAR_LDS: items are LdsItem,
-// workgroup q runs items [wstart[q], wstart[q+1]), nwg workgroups.  VAR_D*:
+// workgroup q runs items [wstart[q], wstart[q+1]), nwg workgroups (in mixed
+// precision: the FP32 launch, then the FP64 pass over cand).  VAR_D*:
 // items are DirectItem, one workgroup per item.
 struct BatchLaunch {
   int variant;
@@ -51,6 +52,10 @@ struct BatchLaunch {
   const int32_t* wstart;  // device, nwg + 1 entries (VAR_LDS)
   int nitems;
   int nwg;
+  // VAR_LDS, mixed precision: every tile of the launch's patches once, in
+  // a scattering order; the FP64 pass examines them (device, ncand)
+  const TileRef* cand;
+  int ncand;
 };
 hipError_t launch_batch_o4(const BatchLaunch& B, const Gauge& G, int stage,
                            int precision, hipStream_t st);

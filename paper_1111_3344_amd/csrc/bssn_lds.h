@@ -763,6 +763,114 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Many patches, mixed precision, first launch: the FP32 tiles, with split
+// (1 or 2) workgroups per work list position.  Workgroup b' stands for
+// workgroup b of the list's launch of nwg on the same XCD (b' mod 8 = b mod
+// 8) and runs part h of every item of b's list.
+template <int ORDER>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(ORDER == 4 ? 2 : 1,
+                                       ORDER == 4 ? 2 : 1)))
+    k_stage_lds_batch_f32(const Patch* __restrict__ patches,
+                          const LdsItem* __restrict__ items,
+                          const int32_t* __restrict__ wstart, const Gauge G,
+                          const int stage, const int nwg, const int split) {
+  using Geo = GeoF32<ORDER>;
+  __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
+  __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  const int bp = blockIdx.x;
+  const bool xcd = (nwg & 7) == 0;
+  const int b = xcd ? 8 * ((bp >> 3) / split) + (bp & 7) : bp / split;
+  const int h = xcd ? (bp >> 3) % split : bp % split;
+  const int q = walk_pos(b, nwg);
+  const int i0 = wstart[q], i1 = wstart[q + 1];
+  for (int i = i0; i < i1; ++i) {
+    const LdsItem it = items[i];
+    const Patch P = patches[it.patch];
+    const int n = it.thi - it.tlo;
+    const int lo = it.tlo + n * h / split, hi = it.tlo + n * (h + 1) / split;
+    const Walk w = walk_contig(lo, hi - lo, it.ntx, it.ntz);
+    lds_tiles<ORDER, TP_F32, true, Geo>(P, G, stage, w, ring, sc);
+    __builtin_amdgcn_s_barrier();  // every wave is done with ring and sc
+  }
+}
+
+// Many patches, mixed precision, second launch: the FP64 tiles.  Workgroup
+// b examines the candidates [lo, hi) of an even split of cand (every tile of
+// the launch once, scattered by the plan), as k_stage_lds_f64tiles does.
+template <int ORDER>
+__global__ void __launch_bounds__(256)
+    k_stage_lds_batch_f64tiles(const Patch* __restrict__ patches,
+                               const TileRef* __restrict__ cand,
+                               const int ncand, const Gauge G,
+                               const int stage) {
+  using Geo = TileGeo<ORDER>;
+  __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
+  __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  __shared__ double wmin[4][kF64Chunk];
+  __shared__ int lpatch[kF64Chunk], ltile[kF64Chunk];
+  __shared__ int nlist;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tx = lane & 15, ty = lane >> 4;
+  int lo, hi;
+  walk_range(blockIdx.x, gridDim.x, ncand, lo, hi);
+  for (int c0 = lo; c0 < hi; c0 += kF64Chunk) {
+    const int nc = hi - c0 < kF64Chunk ? hi - c0 : kF64Chunk;
+    for (int c1 = 0; c1 < nc; c1 += 8) {
+      double a[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        a[c] = 1.0e300;
+        if (c1 + c < nc) {
+          const TileRef r = cand[c0 + c1 + c];
+          const Patch& P = patches[r.patch];
+          const int ntx = (P.n[0] + kLdsTile[0] - 1) / kLdsTile[0];
+          const int ntz = (P.n[2] + kLdsTile[2] - 1) / kLdsTile[2];
+          int x0, y0, z0;
+          tile_origin(r.tile, ntx, ntz, x0, y0, z0);
+          const int x = x0 + tx, y = y0 + ty, z = z0 + wave, g = P.ghost;
+          if (x < P.n[0] && y < P.n[1] && z < P.n[2])
+            a[c] = P.u_s[int64_t(ALP) * P.sf + int64_t(z + g) * P.sz +
+                         int64_t(y + g) * P.sy + x + g];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+          a[c] = fmin(a[c], __shfl_xor(a[c], off, 64));
+        if (lane == 0 && c1 + c < nc) wmin[wave][c1 + c] = a[c];
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int n = 0;
+      for (int c = 0; c < nc; ++c) {
+        const double m =
+            fmin(fmin(wmin[0][c], wmin[1][c]), fmin(wmin[2][c], wmin[3][c]));
+        if (m < G.alpha_thr) {
+          const TileRef r = cand[c0 + c];
+          lpatch[n] = r.patch;
+          ltile[n] = r.tile;
+          ++n;
+        }
+      }
+      nlist = n;
+    }
+    __syncthreads();
+    const int n = nlist;
+    for (int k = 0; k < n; ++k) {
+      const Patch P = patches[lpatch[k]];
+      const ListWalk w{(const lds_int*)(ltile + k), 1,
+                       (P.n[0] + kLdsTile[0] - 1) / kLdsTile[0],
+                       (P.n[2] + kLdsTile[2] - 1) / kLdsTile[2]};
+      lds_tiles<ORDER, TP_F64, true>(P, G, stage, w, ring, sc);
+      __syncthreads();  // every wave is done with ring and sc
+    }
+    __syncthreads();  // wmin and the lists are reused
+  }
+}
+
 template <int ORDER>
 inline TileMap lds_tile_map(const Patch& P) {
   using Geo = TileGeo<ORDER>;
@@ -808,24 +916,6 @@ inline bool lds_path_ok(const Patch& P) {
 
 namespace bssn {
 
-// A multiplier coprime to n near n times the golden ratio's fraction:
-// i -> (i * perm) mod n is then a permutation of 0 .. n - 1 that scatters
-// neighbours.
-inline int tile_perm(int n) {
-  if (n <= 1) return 1;
-  int64_t p = int64_t(double(n) * 0.6180339887498949);
-  if (p < 1) p = 1;
-  for (;; ++p) {
-    int64_t a = p, b = n;
-    while (b) {
-      const int64_t r = a % b;
-      a = b;
-      b = r;
-    }
-    if (a == 1) return int(p % n == 0 ? 1 : p);
-  }
-}
-
 // precision 0: one FP64 launch.  Mixed: the FP32 tiles (two workgroups per
 // CU at order 4), then the FP64 tiles; both launches take the same per-tile
 // decision from the stage input, so each tile is written exactly once.
@@ -849,7 +939,7 @@ hipError_t launch_stage_lds(const Patch& P, const Gauge& G, int stage,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_stage_lds_f64tiles<ORDER>), dim3(nwg), dim3(256), 0,
-                     st, P, G, stage, M, tile_perm(M.ntiles));
+                     st, P, G, stage, M, int(tile_perm(M.ntiles)));
   return hipGetLastError();
 }
 
@@ -891,12 +981,26 @@ hipError_t launch_batch_t(const BatchLaunch& B, const Gauge& G, int stage,
                           int precision, hipStream_t st) {
   if (B.variant == VAR_LDS) {
     const LdsItem* it = static_cast<const LdsItem*>(B.items);
-    if (precision == 0)
+    if (precision == 0) {
       hipLaunchKernelGGL((k_stage_lds_batch<ORDER, TP_F64>), dim3(B.nwg),
                          dim3(256), 0, st, B.patches, it, B.wstart, G, stage);
-    else
+      return hipGetLastError();
+    }
+    if (!B.cand) {  // no candidate list: one launch with both paths
       hipLaunchKernelGGL((k_stage_lds_batch<ORDER, TP_MIXED>), dim3(B.nwg),
                          dim3(256), 0, st, B.patches, it, B.wstart, G, stage);
+      return hipGetLastError();
+    }
+    const int split = ORDER == 4 ? 2 : 1;
+    hipLaunchKernelGGL((k_stage_lds_batch_f32<ORDER>), dim3(split * B.nwg),
+                       dim3(256), 0, st, B.patches, it, B.wstart, G, stage,
+                       B.nwg, split);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || B.ncand <= 0) return e;
+    const int nwg64 = B.ncand < B.nwg ? B.ncand : B.nwg;
+    hipLaunchKernelGGL((k_stage_lds_batch_f64tiles<ORDER>), dim3(nwg64),
+                       dim3(256), 0, st, B.patches, B.cand, B.ncand, G,
+                       stage);
     return hipGetLastError();
   }
   if (B.variant <= VAR_LDS || B.variant >= NVAR) return hipErrorInvalidValue;

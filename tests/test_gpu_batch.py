@@ -220,19 +220,20 @@ def test_forced_tiles_bitwise_and_oracle(B, tile, precision):
     plan.destroy()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("mode", [0, 0x200])
-def test_graph_replays_match_eager_every_step(B, mode):
+def test_graph_replays_match_eager_every_step(B, mode, precision):
     """The step graph replayed one step at a time, with eager torch work and
     synchronisations between replays, equals eager launches of the same
-    kernels after every step (persistent and per-patch launch modes)."""
+    kernels after every step (persistent and per-patch launch modes; in
+    mixed precision each LDS stage is two launches)."""
     grids, us = host_set(6, 303, 17, 45)
     ga = device_set(B, us)
     gb = device_set(B, us)
     flags = B.BSSN_BATCH_TILE(0) | mode
-    graph = B.batch_patches_plan(grids, B.Params(), *ga, 0.03125,
-                                 autotune=flags)
-    eager = B.batch_patches_plan(grids, B.Params(), *gb, 0.03125,
-                                 autotune=flags)
+    prm = B.Params(precision=precision)
+    graph = B.batch_patches_plan(grids, prm, *ga, 0.03125, autotune=flags)
+    eager = B.batch_patches_plan(grids, prm, *gb, 0.03125, autotune=flags)
     assert B.batch_patches_launch_mode(graph) == mode
     for step in range(4):
         B.batch_patches(graph, 1)
@@ -246,3 +247,41 @@ def test_graph_replays_match_eager_every_step(B, mode):
             assert np.array_equal(x[p], y[p]), (step, p)
     graph.destroy()
     eager.destroy()
+
+
+def _tile_min(a, tile=(4, 4, 16)):
+    nz, ny, nx = a.shape
+    tz, ty, tx = tile
+    p = np.pad(a, ((0, -nz % tz), (0, -ny % ty), (0, -nx % tx)),
+               constant_values=np.inf)
+    Z, Y, X = p.shape
+    return p.reshape(Z // tz, tz, Y // ty, ty, X // tx, tx).min(axis=(1, 3, 5))
+
+
+def test_batched_mixed_many_fp64_tiles_bitwise(B):
+    """Smooth data with the lapse threshold at the median tile minimum, so
+    that FP64 tiles are scattered over every patch: the batched FP32 launch
+    and FP64 pass == the per-patch launches, bitwise, after two steps."""
+    specs = I.patches(8, seed=919, nlo=17, nhi=50)
+    grids = [g for g, _, _ in specs]
+    us = [I.smooth_random(g, seed=30 + i) for i, g in enumerate(grids)]
+    mins = np.concatenate([_tile_min(g.interior(u)[I.ALP]).ravel()
+                           for g, u in zip(grids, us)])
+    thr = float(np.median(mins))
+    frac = float((mins < thr).mean())
+    print(f"[batch-mixed] {mins.size} tiles, FP64 fraction {frac:.2f} at "
+          f"threshold {thr:.4f}", flush=True)
+    assert 0.3 < frac < 0.7
+    bufs = device_set(B, us)
+    prm = B.Params(precision=1, fp64_alpha_threshold=thr)
+    plan = B.batch_patches_plan(grids, prm, *bufs, 0.03125,
+                                autotune=B.BSSN_BATCH_TILE(0))
+    B.batch_patches(plan, 2)
+    got = results(grids, bufs[0])
+    reset(bufs, us)
+    B.batch_patches_unbatched(plan, 2)
+    ref = results(grids, bufs[0])
+    for p, (x, y) in enumerate(zip(got, ref)):
+        assert np.array_equal(x, y), f"patch {p} differs"
+        assert np.isfinite(x).all()
+    plan.destroy()
