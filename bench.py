@@ -203,12 +203,23 @@ def summarize_profile(dirs, order=4):
     Lines starting with '#' are the summary; the 'key: value' lines at the
     end are the figures bench.py reads back for the FP64 stage kernel of the
     given order (HBM bytes per launch scaled by the copy calibration, VALU
-    FLOPs per launch), stamped with the hash of the kernel sources."""
+    FLOPs per launch) and, prefixed mixed_, for the two launches of a mixed
+    stage, stamped with the hash of the kernel sources."""
     import glob
     import collections
     import re
     out = []
-    stage = re.compile(r"k_stage_lds<\s*%d\s*,\s*false\s*>" % order)
+    kernels = (("", re.compile(r"k_stage_lds<\s*%d\s*>\(" % order)),
+               ("mixed_f32_", re.compile(r"k_stage_lds_f32<\s*%d\s*>\(" %
+                                         order)),
+               ("mixed_f64pass_", re.compile(
+                   r"k_stage_lds_f64tiles<\s*%d\s*>\(" % order)))
+
+    def tag(name):
+        for t, rx in kernels:
+            if rx.search(name):
+                return t
+        return None
     kv = {}
     for d in dirs:
         for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"),
@@ -224,8 +235,9 @@ def summarize_profile(dirs, order=4):
                 out.append(f"# {len(v):6d} {sum(v) / len(v) / 1e3:9.1f} "
                            f"{min(v) / 1e3:9.1f} {max(v) / 1e3:9.1f} "
                            f"{sum(v) / 1e6:9.2f}  {k[:110]}")
-                if stage.search(k):
-                    kv["avg_launch_us"] = f"{sum(v) / len(v) / 1e3:.2f}"
+                if tag(k) is not None:
+                    kv[tag(k) + "avg_launch_us"] = \
+                        f"{sum(v) / len(v) / 1e3:.2f}"
         for f in sorted(glob.glob(os.path.join(d, "**",
                                                "*counter_collection.csv"),
                                   recursive=True)):
@@ -246,8 +258,8 @@ def summarize_profile(dirs, order=4):
                 for c, v in cs.items():
                     out.append(f"#   {c:26s} dispatches {len(v):4d} avg "
                                f"{sum(v) / len(v):14.6g}  {k[:90]}")
-                    if stage.search(k):
-                        kv[f"{c}_per_launch"] = sum(v) / len(v)
+                    if tag(k) is not None:
+                        kv[f"{tag(k)}{c}_per_launch"] = sum(v) / len(v)
             copies = [did for did in sorted(per)
                       if "copyBuffer" in names[did]][-3:]
             for c in sorted({c for did in copies for c in per[did]}):
@@ -257,22 +269,28 @@ def summarize_profile(dirs, order=4):
                            f"{sum(v) / len(v):.6g}")
                 kv[f"copy_{c}"] = sum(v) / len(v)
     res = [f"source_sha256: {kernel_source_hash()}"]
-    if "avg_launch_us" in kv:
-        res.append(f"avg_launch_us: {kv['avg_launch_us']}")
-    if all(k in kv for k in ("FETCH_SIZE_per_launch", "WRITE_SIZE_per_launch",
-                             "copy_FETCH_SIZE", "copy_WRITE_SIZE")):
-        res += [f"fetch_kib_per_launch: {kv['FETCH_SIZE_per_launch']:.6g}",
-                f"write_kib_per_launch: {kv['WRITE_SIZE_per_launch']:.6g}",
-                f"copy_bytes: {CALIB_BYTES}",
+    for t, _ in kernels:
+        if t + "avg_launch_us" in kv:
+            res.append(f"{t}avg_launch_us: {kv[t + 'avg_launch_us']}")
+    if all(k in kv for k in ("copy_FETCH_SIZE", "copy_WRITE_SIZE")):
+        res += [f"copy_bytes: {CALIB_BYTES}",
                 f"copy_fetch_kib: {kv['copy_FETCH_SIZE']:.6g}",
                 f"copy_write_kib: {kv['copy_WRITE_SIZE']:.6g}"]
-    for prec in ("F64", "F32"):
-        parts = [f"SQ_INSTS_VALU_{o}_{prec}_per_launch"
-                 for o in ("ADD", "MUL", "FMA", "TRANS")]
-        if all(p in kv for p in parts):
-            a, m, fma, tr = (kv[p] for p in parts)
-            res.append(f"valu_flops_{prec.lower()}_per_launch: "
-                       f"{64 * (a + m + tr + 2 * fma):.6g}")
+        for t, _ in kernels:
+            if all(f"{t}{c}_per_launch" in kv
+                   for c in ("FETCH_SIZE", "WRITE_SIZE")):
+                res += [f"{t}fetch_kib_per_launch: "
+                        f"{kv[t + 'FETCH_SIZE_per_launch']:.6g}",
+                        f"{t}write_kib_per_launch: "
+                        f"{kv[t + 'WRITE_SIZE_per_launch']:.6g}"]
+    for t, _ in kernels:
+        for prec in ("F64", "F32"):
+            parts = [f"{t}SQ_INSTS_VALU_{o}_{prec}_per_launch"
+                     for o in ("ADD", "MUL", "FMA", "TRANS")]
+            if all(p in kv for p in parts):
+                a, m, fma, tr = (kv[p] for p in parts)
+                res.append(f"{t}valu_flops_{prec.lower()}_per_launch: "
+                           f"{64 * (a + m + tr + 2 * fma):.6g}")
     return "\n".join(out + res)
 
 
@@ -295,11 +313,11 @@ def profile_figures(workload, kernel_tag):
     return kv, os.path.relpath(path, ROOT)
 
 
-def traffic_bytes(kv):
-    """Measured HBM bytes per stage launch: each counter scaled by what it
-    reads for a plain copy of known size."""
-    f = float(kv["fetch_kib_per_launch"]) * 1024.0
-    w = float(kv["write_kib_per_launch"]) * 1024.0
+def traffic_bytes(kv, prefix=""):
+    """Measured HBM bytes per launch of the kernel the prefix names: each
+    counter scaled by what it reads for a plain copy of known size."""
+    f = float(kv[prefix + "fetch_kib_per_launch"]) * 1024.0
+    w = float(kv[prefix + "write_kib_per_launch"]) * 1024.0
     fc = float(kv["copy_fetch_kib"]) * 1024.0
     wc = float(kv["copy_write_kib"]) * 1024.0
     cb = float(kv["copy_bytes"])
@@ -480,7 +498,7 @@ def main():
         calibrate_copy(torch)
     f = res["f64"]
     lds = args.path == "auto"
-    kernel = f"k_stage_lds<{order},false>" if lds else f"k_stage<{order},...>"
+    kernel = f"k_stage_lds<{order}>" if lds else f"k_stage<{order},...>"
     kv, tsrc = (profile_figures(args.workload, f"k_stage_lds_o{order}")
                 if lds else (None, "no counter summary for this kernel"))
     traffic = traffic_bytes(kv) if kv and "fetch_kib_per_launch" in kv \
@@ -531,6 +549,23 @@ def main():
                                                HBM_PEAK_GBS, 4),
                         "achieved_gbs": round(m["achieved_gbs"], 1),
                         "stage_kernel_ms": m["stage_kernel_ms"]}
+        if lds:
+            out["mixed"]["kernels"] = (
+                f"k_stage_lds_f32<{order}> (FP32 tiles) then "
+                f"k_stage_lds_f64tiles<{order}> (FP64 tiles), per stage")
+            if kv and "mixed_f32_fetch_kib_per_launch" in kv:
+                t32 = traffic_bytes(kv, "mixed_f32_")
+                t64 = (traffic_bytes(kv, "mixed_f64pass_") if
+                       "mixed_f64pass_fetch_kib_per_launch" in kv else 0.0)
+                out["mixed"]["traffic"] = round(t32 + t64)
+                out["mixed"]["traffic_unit"] = ("HBM bytes per stage (both "
+                                                "launches, mean of the 4 "
+                                                "stages)")
+                out["mixed"]["traffic_source"] = tsrc
+            for t in ("mixed_f32_", "mixed_f64pass_"):
+                if kv and t + "avg_launch_us" in kv:
+                    out["mixed"][t[6:] + "profiled_avg_launch_us"] = float(
+                        kv[t + "avg_launch_us"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

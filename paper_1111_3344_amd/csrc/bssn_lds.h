@@ -407,8 +407,9 @@ __device__ __forceinline__ void tile_origin(int t, int ntx, int ntz, int& x0,
 //   contiguous walk (bx = 0): tiles tlo + k of the TileMap numbering
 //     (z fastest within an (x, y) column); nk = count, c = 0;
 //   blocked walk (single patches whose tile grid divides into blocks of
-//     bx x by x bz = 32 tiles): the 32 workgroups of one XCD hold one tile
-//     each of a block, step through the block's column together in z by
+//     bx x by x bz = 32 tiles, or 64 with two workgroups per CU): the
+//     workgroups of one XCD hold one tile each of a block, step through
+//     the block's column together in z by
 //     bz tiles, then move on to the XCD's next block (blocks c*8 + xcd).
 //     Neighbouring tiles in x, y and z are then fetched at the same time on
 //     one XCD, and between two z-steps the L2 only has to keep the overlap
@@ -668,15 +669,62 @@ struct ListWalk {
   }
 };
 
+// Minimum lapse over the points of P's tile at (x0, y0, z0), read from
+// global memory by one thread: the value tile_lapse_min takes from the
+// centre block in the FP32 launch (the same points; fmin is exact, so the
+// order does not matter).
+__device__ __forceinline__ double tile_lapse_min_global(const Patch& P,
+                                                        int x0, int y0,
+                                                        int z0) {
+  const int g = P.ghost;
+  const int nx = P.n[0] - x0 < kLdsTile[0] ? P.n[0] - x0 : kLdsTile[0];
+  const int ny = P.n[1] - y0 < kLdsTile[1] ? P.n[1] - y0 : kLdsTile[1];
+  const int nz = P.n[2] - z0 < kLdsTile[2] ? P.n[2] - z0 : kLdsTile[2];
+  const double* a = P.u_s + int64_t(ALP) * P.sf + int64_t(z0 + g) * P.sz +
+                    int64_t(y0 + g) * P.sy + x0 + g;
+  double m = 1.0e300;
+  for (int dz = 0; dz < nz; ++dz)
+    for (int dy = 0; dy < ny; ++dy) {
+      const double* row = a + int64_t(dz) * P.sz + int64_t(dy) * P.sy;
+      if (nx == kLdsTile[0]) {
+#pragma unroll
+        for (int dx = 0; dx < kLdsTile[0]; ++dx) m = fmin(m, row[dx]);
+      } else {
+        for (int dx = 0; dx < nx; ++dx) m = fmin(m, row[dx]);
+      }
+    }
+  return m;
+}
+
+// Writes val of every thread whose flag is set to list, in thread order,
+// and returns their number (the same in every thread).  wcnt: 4 ints of
+// LDS.  Contains the barriers that make list readable afterwards.
+__device__ __forceinline__ int compact_flags(bool f, int val, int* list,
+                                             int* wcnt) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t mask = __builtin_amdgcn_ballot_w64(f);
+  if (lane == 0) wcnt[wave] = __builtin_popcountll(mask);
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    base += w < wave ? wcnt[w] : 0;
+    tot += wcnt[w];
+  }
+  const int below = __builtin_amdgcn_mbcnt_hi(
+      uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0));
+  if (f) list[base + below] = val;
+  __syncthreads();
+  return tot;
+}
+
 // One patch, mixed precision, second launch: the FP64 tiles.  Workgroup b
 // examines the tiles t = (i * perm) mod ntiles for i in its share of an
-// even split of 0 .. ntiles - 1.  perm is coprime to ntiles, so every tile
-// is examined exactly once, and the tiles around a puncture (neighbours in
-// the numbering) land on many workgroups.  Per chunk of kF64Chunk tiles it
-// takes each tile's minimum lapse over its points from global memory (the
-// value tile_lapse_min finds in the FP32 launch, since fmin is exact), then
-// runs the tiles below the threshold through the FP64 pipeline.
-constexpr int kF64Chunk = 64;
+// even split of 0 .. ntiles - 1, one tile per thread at a time.  perm is
+// coprime to ntiles, so every tile is examined exactly once, and the tiles
+// around a puncture (neighbours in the numbering) land on many workgroups.
+// The tiles whose minimum lapse is below the threshold run through the FP64
+// pipeline.
 template <int ORDER>
 __global__ void __launch_bounds__(256)
     k_stage_lds_f64tiles(const Patch P, const Gauge G, const int stage,
@@ -684,58 +732,26 @@ __global__ void __launch_bounds__(256)
   using Geo = TileGeo<ORDER>;
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
-  __shared__ double wmin[4][kF64Chunk];
-  __shared__ int list[kF64Chunk];
-  __shared__ int nlist;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tx = lane & 15, ty = lane >> 4;
-  const int g = P.ghost;
-  const double* alp = P.u_s + int64_t(ALP) * P.sf;
+  __shared__ int list[256];
+  __shared__ int wcnt[4];
+  const int tid = threadIdx.x;
   int lo, hi;
   walk_range(blockIdx.x, gridDim.x, M.ntiles, lo, hi);
-  for (int c0 = lo; c0 < hi; c0 += kF64Chunk) {
-    const int nc = hi - c0 < kF64Chunk ? hi - c0 : kF64Chunk;
-    // wave w reduces plane w of every tile of the chunk, 8 loads in flight
-    for (int c1 = 0; c1 < nc; c1 += 8) {
-      double a[8];
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        a[c] = 1.0e300;
-        if (c1 + c < nc) {
-          int x0, y0, z0;
-          tile_origin(int((int64_t(c0 + c1 + c) * perm) % M.ntiles), M.ntx,
-                      M.ntz, x0, y0, z0);
-          const int x = x0 + tx, y = y0 + ty, z = z0 + wave;
-          if (x < P.n[0] && y < P.n[1] && z < P.n[2])
-            a[c] = alp[int64_t(z + g) * P.sz + int64_t(y + g) * P.sy + x + g];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-          a[c] = fmin(a[c], __shfl_xor(a[c], off, 64));
-        if (lane == 0 && c1 + c < nc) wmin[wave][c1 + c] = a[c];
-      }
+  for (int c0 = lo; c0 < hi; c0 += 256) {
+    bool f = false;
+    int t = 0;
+    if (c0 + tid < hi) {
+      t = int((int64_t(c0 + tid) * perm) % M.ntiles);
+      int x0, y0, z0;
+      tile_origin(t, M.ntx, M.ntz, x0, y0, z0);
+      f = tile_lapse_min_global(P, x0, y0, z0) < G.alpha_thr;
     }
-    __syncthreads();
-    if (tid == 0) {
-      int n = 0;
-      for (int c = 0; c < nc; ++c) {
-        const double m =
-            fmin(fmin(wmin[0][c], wmin[1][c]), fmin(wmin[2][c], wmin[3][c]));
-        if (m < G.alpha_thr)
-          list[n++] = int((int64_t(c0 + c) * perm) % M.ntiles);
-      }
-      nlist = n;
-    }
-    __syncthreads();
-    const int n = nlist;
+    const int n = compact_flags(f, t, list, wcnt);
     if (n > 0) {
       const ListWalk w{(const lds_int*)list, n, M.ntx, M.ntz};
       lds_tiles<ORDER, TP_F64, ORDER == 8>(P, G, stage, w, ring, sc);
     }
-    __syncthreads();  // ring, sc, wmin and list are reused
+    __syncthreads();  // ring, sc, list and wcnt are reused
   }
 }
 
@@ -797,7 +813,8 @@ __global__ void __launch_bounds__(256)
 
 // Many patches, mixed precision, second launch: the FP64 tiles.  Workgroup
 // b examines the candidates [lo, hi) of an even split of cand (every tile of
-// the launch once, scattered by the plan), as k_stage_lds_f64tiles does.
+// the launch once, scattered by the plan), one per thread at a time, as
+// k_stage_lds_f64tiles does.
 template <int ORDER>
 __global__ void __launch_bounds__(256)
     k_stage_lds_batch_f64tiles(const Patch* __restrict__ patches,
@@ -807,67 +824,34 @@ __global__ void __launch_bounds__(256)
   using Geo = TileGeo<ORDER>;
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
-  __shared__ double wmin[4][kF64Chunk];
-  __shared__ int lpatch[kF64Chunk], ltile[kF64Chunk];
-  __shared__ int nlist;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tx = lane & 15, ty = lane >> 4;
+  __shared__ int list[256], ltile[256];
+  __shared__ int wcnt[4];
+  const int tid = threadIdx.x;
   int lo, hi;
   walk_range(blockIdx.x, gridDim.x, ncand, lo, hi);
-  for (int c0 = lo; c0 < hi; c0 += kF64Chunk) {
-    const int nc = hi - c0 < kF64Chunk ? hi - c0 : kF64Chunk;
-    for (int c1 = 0; c1 < nc; c1 += 8) {
-      double a[8];
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        a[c] = 1.0e300;
-        if (c1 + c < nc) {
-          const TileRef r = cand[c0 + c1 + c];
-          const Patch& P = patches[r.patch];
-          const int ntx = (P.n[0] + kLdsTile[0] - 1) / kLdsTile[0];
-          const int ntz = (P.n[2] + kLdsTile[2] - 1) / kLdsTile[2];
-          int x0, y0, z0;
-          tile_origin(r.tile, ntx, ntz, x0, y0, z0);
-          const int x = x0 + tx, y = y0 + ty, z = z0 + wave, g = P.ghost;
-          if (x < P.n[0] && y < P.n[1] && z < P.n[2])
-            a[c] = P.u_s[int64_t(ALP) * P.sf + int64_t(z + g) * P.sz +
-                         int64_t(y + g) * P.sy + x + g];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-          a[c] = fmin(a[c], __shfl_xor(a[c], off, 64));
-        if (lane == 0 && c1 + c < nc) wmin[wave][c1 + c] = a[c];
-      }
+  for (int c0 = lo; c0 < hi; c0 += 256) {
+    bool f = false;
+    if (c0 + tid < hi) {
+      const TileRef r = cand[c0 + tid];
+      const Patch& P = patches[r.patch];
+      const int ntx = (P.n[0] + kLdsTile[0] - 1) / kLdsTile[0];
+      const int ntz = (P.n[2] + kLdsTile[2] - 1) / kLdsTile[2];
+      int x0, y0, z0;
+      tile_origin(r.tile, ntx, ntz, x0, y0, z0);
+      f = tile_lapse_min_global(P, x0, y0, z0) < G.alpha_thr;
     }
+    const int n = compact_flags(f, c0 + tid, list, wcnt);
+    if (tid < n) ltile[tid] = cand[list[tid]].tile;  // for the walks
     __syncthreads();
-    if (tid == 0) {
-      int n = 0;
-      for (int c = 0; c < nc; ++c) {
-        const double m =
-            fmin(fmin(wmin[0][c], wmin[1][c]), fmin(wmin[2][c], wmin[3][c]));
-        if (m < G.alpha_thr) {
-          const TileRef r = cand[c0 + c];
-          lpatch[n] = r.patch;
-          ltile[n] = r.tile;
-          ++n;
-        }
-      }
-      nlist = n;
-    }
-    __syncthreads();
-    const int n = nlist;
     for (int k = 0; k < n; ++k) {
-      const Patch P = patches[lpatch[k]];
+      const Patch P = patches[cand[list[k]].patch];
       const ListWalk w{(const lds_int*)(ltile + k), 1,
                        (P.n[0] + kLdsTile[0] - 1) / kLdsTile[0],
                        (P.n[2] + kLdsTile[2] - 1) / kLdsTile[2]};
       lds_tiles<ORDER, TP_F64, true>(P, G, stage, w, ring, sc);
       __syncthreads();  // every wave is done with ring and sc
     }
-    __syncthreads();  // wmin and the lists are reused
+    __syncthreads();  // the lists and wcnt are reused
   }
 }
 
@@ -883,15 +867,18 @@ inline TileMap lds_tile_map(const Patch& P) {
   return M;
 }
 
-// Blocked walk (Walk with bx > 0) for a launch of 256 workgroups: the first
-// block shape of 32 tiles that divides the tile grid and leaves every XCD
-// at least one block; otherwise the contiguous walk.
+// Blocked walk (Walk with bx > 0) for a launch of 256 or 512 workgroups
+// (one or two per CU): the first block shape of nwg / 8 tiles that divides
+// the tile grid and leaves every XCD at least one block; otherwise the
+// contiguous walk.
 inline void choose_blocks(TileMap& M, int nwg) {
-  static const int shapes[][3] = {{4, 4, 2}, {2, 4, 4}, {4, 2, 4},
-                                  {2, 2, 8}, {4, 8, 1}, {8, 4, 1}};
+  static const int s32[][3] = {{4, 4, 2}, {2, 4, 4}, {4, 2, 4},
+                               {2, 2, 8}, {4, 8, 1}, {8, 4, 1}};
+  static const int s64[][3] = {{4, 4, 4}, {4, 8, 2}, {8, 4, 2},
+                               {2, 8, 4}, {4, 2, 8}, {8, 8, 1}};
   M.bx = M.by = M.bz = 0;
-  if (nwg != 256) return;
-  for (const auto& b : shapes) {
+  if (nwg != 256 && nwg != 512) return;
+  for (const auto& b : (nwg == 256 ? s32 : s64)) {
     if (M.ntx % b[0] || M.nty % b[1] || M.ntz % b[2]) continue;
     if ((M.ntx / b[0]) * (M.nty / b[1]) < 8) continue;
     M.bx = b[0];

@@ -16,7 +16,10 @@ HDR = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id",
        "LDS_Block_Size", "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count",
        "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp",
        "End_Timestamp"]
-STAGE = "void bssn::k_stage_lds<4, false>(bssn::Patch, bssn::Gauge, int)"
+STAGE = ("void bssn::k_stage_lds<4>(bssn::Patch, bssn::Gauge, int, "
+         "bssn::TileMap)")
+F32 = ("void bssn::k_stage_lds_f32<4>(bssn::Patch, bssn::Gauge, int, "
+       "bssn::TileMap)")
 
 
 def test_more_than_one_gpu_is_refused():
@@ -42,14 +45,19 @@ def test_summary_scales_by_the_copy_calibration(tmp_path, monkeypatch):
     _write(f / "run_counter_collection.csv",
            [(1, copy, "FETCH_SIZE", 7.0)] +
            [(2 + i, STAGE, "FETCH_SIZE", 1000.0) for i in range(4)] +
+           [(10 + i, F32, "FETCH_SIZE", 900.0) for i in range(4)] +
            [(6 + i, copy, "FETCH_SIZE", 524288.0) for i in range(3)])
     _write(w / "run_counter_collection.csv",
            [(2 + i, STAGE, "WRITE_SIZE", 500.0) for i in range(4)] +
+           [(10 + i, F32, "WRITE_SIZE", 400.0) for i in range(4)] +
            [(6 + i, copy, "WRITE_SIZE", 1048576.0) for i in range(3)])
     text = bench.summarize_profile([str(f), str(w)], 4)
     kv = dict(l.split(": ", 1) for l in text.splitlines()
               if not l.startswith("#"))
     assert float(kv["fetch_kib_per_launch"]) == 1000.0
+    assert float(kv["mixed_f32_fetch_kib_per_launch"]) == 900.0
+    assert float(kv["mixed_f32_write_kib_per_launch"]) == 400.0
+    assert "mixed_f64pass_fetch_kib_per_launch" not in kv
     assert float(kv["copy_fetch_kib"]) == 524288.0   # last 3 copies only
     # FETCH reads half the copied bytes here, WRITE all of them
     assert bench.traffic_bytes(kv) == pytest.approx(2 * 1000 * 1024 +
