@@ -25,8 +25,14 @@
 // in the order-4 FP64 kernel its loads are issued three phases before the
 // end of the point function.
 //
-// Tiles are walked persistently (Walk): in blocks of 32 tiles per XCD
-// stepping together in z where the tile grid allows, else in contiguous
+// Mixed precision runs as two launches per stage: k_stage_lds_f32 holds
+// only the FP32 point function (at order 4 with a ring of three boxes, so
+// that two workgroups share a CU) and skips the tiles whose minimum lapse
+// is below the threshold; k_stage_lds_f64tiles then finds those tiles by
+// the same test and runs them in FP64.
+//
+// Tiles are walked persistently (Walk): in blocks of 32 (or 64) tiles per
+// XCD stepping together in z where the tile grid allows, else in contiguous
 // z-column runs, so tiles whose halos overlap are in flight on one XCD and
 // meet in its L2.
 #pragma once
@@ -359,7 +365,7 @@ struct LdLds {
   }
   // With CORNER, pc is the thread's stencil corner, so every tap is a
   // non-negative immediate offset (fewer address adds, more ds_read2 pairs;
-  // measured faster for the mixed and the order-8 kernels, slower for the
+  // measured faster for the FP32 and the order-8 kernels, slower for the
   // order-4 FP64 one).
   static constexpr int kC =
       CORNER ? Geo::R * (1 + Geo::W + Geo::W * Geo::H) : 0;
@@ -446,12 +452,12 @@ __device__ __forceinline__ Walk walk_contig(int tlo, int n, int ntx,
 
 // Arithmetic of the tiles of an LDS kernel:
 //   TP_F64   FP64 everywhere;
-//   TP_MIXED per tile, FP32 stencils and algebra unless the tile's minimum
-//            lapse is below G.alpha_thr, then FP64 (both in one kernel);
-//   TP_F32   the FP32 tiles of that split only: a tile that needs FP64 runs
-//            through the pipeline without arithmetic and is left to
-//            k_stage_lds_f64tiles, which finds it by the same test.
-enum : int { TP_F64 = 0, TP_MIXED = 1, TP_F32 = 2 };
+//   TP_F32   the FP32 launch of a mixed-precision stage: FP32 stencils and
+//            algebra on every tile whose minimum lapse is at least
+//            G.alpha_thr; a tile below it runs through the pipeline without
+//            arithmetic and is left to the FP64 pass (k_stage_lds_f64tiles,
+//            k_stage_lds_batch_f64tiles), which finds it by the same test.
+enum : int { TP_F64 = 0, TP_F32 = 1 };
 
 // Minimum lapse over the tile's points, taken from the centre block (which
 // holds all 256 of them) in every wave, so that each wave reaches the same
@@ -531,9 +537,9 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     const bool active = x < P.n[0] && y < P.n[1] && z < P.n[2];
     const int g = P.ghost;
     // early epilogue loads where the registers allow (order 4, FP64);
-    // corner-based tap addressing for the mixed and order-8 kernels
+    // corner-based tap addressing for the FP32 and order-8 kernels
     constexpr bool early = Geo::EARLY_EPI && TP == TP_F64;
-    constexpr bool corner = TP != TP_F64 || ORDER == 8;
+    constexpr bool corner = TP == TP_F32 || ORDER == 8;
     LdLds<Geo, early, corner> ld;
     ld.P = &P;
     ld.ring = ring;
@@ -570,16 +576,11 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
                                        nbytes, active);
     } else {
       if (tile_lapse_min(sc, P, x, y, z0, lane) < G.alpha_thr) {
-        if constexpr (TP == TP_F32) {
-          // left to the FP64 pass: keep the pipeline going (waits,
-          // barriers, prefetches) through the tile's other phases
+        // left to the FP64 pass: keep the pipeline going (waits, barriers,
+        // prefetches) through the tile's other phases
 #pragma unroll
-          for (int p = 1; p < NSLOT; ++p) ld.phase(p);
-          computed = false;
-        } else {
-          tile_point<ORDER, double, early>(ld, P, G, stage, xc, yc, zc, vc,
-                                           nbytes, active);
-        }
+        for (int p = 1; p < NSLOT; ++p) ld.phase(p);
+        computed = false;
       } else {
         tile_point<ORDER, float, early>(ld, P, G, stage, xc, yc, zc, vc,
                                         nbytes, active);
@@ -755,9 +756,9 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Many patches: workgroup b runs the items [wstart[q], wstart[q+1]) for
-// q = walk_pos(b).  TP is TP_F64 or TP_MIXED.
-template <int ORDER, int TP>
+// Many patches, FP64: workgroup b runs the items [wstart[q], wstart[q+1])
+// for q = walk_pos(b).
+template <int ORDER>
 __global__ void __launch_bounds__(256)
     k_stage_lds_batch(const Patch* __restrict__ patches,
                       const LdsItem* __restrict__ items,
@@ -774,7 +775,7 @@ __global__ void __launch_bounds__(256)
     const Walk w = walk_contig(it.tlo, it.thi - it.tlo, it.ntx, it.ntz);
     // trimmed DMA always: many patches at once miss L2 more often, so the
     // saved traffic matters more than the register
-    lds_tiles<ORDER, TP, true>(P, G, stage, w, ring, sc);
+    lds_tiles<ORDER, TP_F64, true>(P, G, stage, w, ring, sc);
     __builtin_amdgcn_s_barrier();  // every wave is done with ring and sc
   }
 }
@@ -969,15 +970,11 @@ hipError_t launch_batch_t(const BatchLaunch& B, const Gauge& G, int stage,
   if (B.variant == VAR_LDS) {
     const LdsItem* it = static_cast<const LdsItem*>(B.items);
     if (precision == 0) {
-      hipLaunchKernelGGL((k_stage_lds_batch<ORDER, TP_F64>), dim3(B.nwg),
-                         dim3(256), 0, st, B.patches, it, B.wstart, G, stage);
+      hipLaunchKernelGGL((k_stage_lds_batch<ORDER>), dim3(B.nwg), dim3(256),
+                         0, st, B.patches, it, B.wstart, G, stage);
       return hipGetLastError();
     }
-    if (!B.cand) {  // no candidate list: one launch with both paths
-      hipLaunchKernelGGL((k_stage_lds_batch<ORDER, TP_MIXED>), dim3(B.nwg),
-                         dim3(256), 0, st, B.patches, it, B.wstart, G, stage);
-      return hipGetLastError();
-    }
+    if (!B.cand) return hipErrorInvalidValue;  // the plan always builds it
     const int split = ORDER == 4 ? 2 : 1;
     hipLaunchKernelGGL((k_stage_lds_batch_f32<ORDER>), dim3(split * B.nwg),
                        dim3(256), 0, st, B.patches, it, B.wstart, G, stage,
