@@ -873,7 +873,7 @@ inline TileMap lds_tile_map(const Patch& P) {
 // the tile grid and leaves every XCD at least one block; otherwise the
 // contiguous walk.
 inline void choose_blocks(TileMap& M, int nwg) {
-  static const int s32[][3] = {{4, 4, 2}, {2, 4, 4}, {4, 2, 4},
+  static const int s32[][3] = {{4, 2, 4}, {4, 4, 2}, {2, 4, 4},
                                {2, 2, 8}, {4, 8, 1}, {8, 4, 1}};
   static const int s64[][3] = {{4, 4, 4}, {4, 8, 2}, {8, 4, 2},
                                {2, 8, 4}, {4, 2, 8}, {8, 8, 1}};

@@ -161,6 +161,12 @@ SPLIT_CASES = {
         lambda: I.GridSpec((10, 3, 2), 3, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0),
                            I.BC_STATIC),
         lambda g: I.smooth_random(g, seed=3), 4, 2.0),
+    # tile grid 8 x 16 x 4: the FP32 launch (512 workgroups) takes its
+    # blocked walk with 4 x 4 x 4 blocks
+    "smooth-blocked-half": (
+        lambda: I.GridSpec((128, 64, 16), 3, (0.1, 0.11, 0.12),
+                           (-6.3, -3.4, -0.9), I.BC_STATIC),
+        lambda g: I.smooth_random(g, seed=17), 4, 0.8893),
     "order8-smooth-half": (
         lambda: I.GridSpec((40, 22, 13), 5, (0.1, 0.12, 0.11),
                            (-2.0, -1.3, -0.7), I.BC_STATIC),

@@ -120,6 +120,11 @@ CASES = {
         lambda: I.GridSpec((124, 64, 40), 5, (0.1, 0.11, 0.12),
                            (-6.1, -3.5, -2.4), I.BC_STATIC),
         lambda g: I.smooth_random(g, seed=13), dict(fd_order=8)),
+    # tile grid 8 x 8 x 12: blocks of 4 x 2 x 4 tiles, 4 deep in z
+    "smooth-static-blocked-z4": (
+        lambda: I.GridSpec((124, 32, 48), 3, (0.1, 0.11, 0.12),
+                           (-6.1, -1.7, -2.8), I.BC_STATIC),
+        lambda g: I.smooth_random(g, seed=14), {}),
 }
 
 
@@ -158,7 +163,8 @@ def test_rhs_matches_oracle(B, case, path):
     ("smooth-periodic", 2, 0.02),
     ("bl-two-punctures-48", 2, 0.1),
     ("order8-smooth-static", 1, 0.02),
-    ("smooth-static-blocked", 2, 0.02)])
+    ("smooth-static-blocked", 2, 0.02),
+    ("smooth-static-blocked-z4", 1, 0.02)])
 def test_rk4_steps_match_oracle(B, case, nsteps, dt, path):
     gfn, dfn, kw = CASES[case]
     g = gfn()
