@@ -871,10 +871,14 @@ inline TileMap lds_tile_map(const Patch& P) {
 // Blocked walk (Walk with bx > 0) for a launch of 256 or 512 workgroups
 // (one or two per CU): the first block shape of nwg / 8 tiles that divides
 // the tile grid and leaves every XCD at least one block; otherwise the
-// contiguous walk.
+// contiguous walk.  Order 8 (a 14-plane box) measured best with blocks 2
+// tiles deep in z, order 4 with 4.
+template <int ORDER>
 inline void choose_blocks(TileMap& M, int nwg) {
-  static const int s32[][3] = {{4, 2, 4}, {4, 4, 2}, {2, 4, 4},
-                               {2, 2, 8}, {4, 8, 1}, {8, 4, 1}};
+  static const int s32[][3] = {
+      {4, ORDER == 8 ? 4 : 2, ORDER == 8 ? 2 : 4},
+      {4, ORDER == 8 ? 2 : 4, ORDER == 8 ? 4 : 2},
+      {2, 4, 4}, {2, 2, 8}, {4, 8, 1}, {8, 4, 1}};
   static const int s64[][3] = {{4, 4, 4}, {4, 8, 2}, {8, 4, 2},
                                {2, 8, 4}, {4, 2, 8}, {8, 8, 1}};
   M.bx = M.by = M.bz = 0;
@@ -913,7 +917,7 @@ hipError_t launch_stage_lds(const Patch& P, const Gauge& G, int stage,
   TileMap M = lds_tile_map<ORDER>(P);
   const int nwg = M.ntiles < nwg_max ? M.ntiles : nwg_max;
   if (precision == 0) {
-    choose_blocks(M, nwg);
+    choose_blocks<ORDER>(M, nwg);
     hipLaunchKernelGGL((k_stage_lds<ORDER>), dim3(nwg), dim3(256), 0, st, P,
                        G, stage, M);
     return hipGetLastError();
@@ -921,7 +925,7 @@ hipError_t launch_stage_lds(const Patch& P, const Gauge& G, int stage,
   const int per_cu = ORDER == 4 ? 2 : 1;
   const int nwg32 = M.ntiles < per_cu * nwg_max ? M.ntiles : per_cu * nwg_max;
   TileMap M32 = M;
-  choose_blocks(M32, nwg32);
+  choose_blocks<ORDER>(M32, nwg32);
   hipLaunchKernelGGL((k_stage_lds_f32<ORDER>), dim3(nwg32), dim3(256), 0, st,
                      P, G, stage, M32);
   hipError_t e = hipGetLastError();
