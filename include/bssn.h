@@ -170,6 +170,31 @@ int bssn_constraints(const bssn_grid* grid, const bssn_params* params,
                      const double* centres, int ncent, double r_exc,
                      double* norms, void* stream);
 
+/* Radiative (Sommerfeld-type) outer boundary (section "Spacetime Curvature
+ * Evolution", boundary conditions): the right-hand side on the ghost layers
+ * of a static grid, which then become evolved boundary points.  Every
+ * component X is taken to be an outgoing spherical wave X0 + u(r - v0 t)/r
+ * near the boundary, giving the wave part
+ *   S = -v0 (x^i d_i X)/r - v0 (X - X0)/r    (r = |x|, x the coordinates),
+ * with second-order differences (centred, one-sided at the storage edge);
+ * the rest of the source decays as r^-power and is carried outward from the
+ * inward neighbour q = p - n (n the outward normal of p's face, edge or
+ * corner): rhs(p) = S(p) + (r_q/r_p)^power (rhs(q) - S(q)).  Layers are
+ * computed innermost first, each from the previous one.
+ *   x0, v0  host, 25 values per slot: value at infinity, wave speed (>= 0)
+ *   power   0..16 (2: the second-order decay the paper assumes)
+ *   u       device state buffer
+ *   rhs     device, the state layout; its interior holds the interior
+ *           right-hand side (e.g. from bssn_rhs) and is read, not written;
+ *           on return its ghost layers hold the boundary right-hand side
+ * The grid must be BSSN_BC_STATIC with ghost >= 3, rhs != u, and the
+ * coordinate origin must not be a ghost point.  Enqueues one launch per
+ * ghost layer on `stream`.  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED,
+ * BSSN_EHIP. */
+int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
+                       const double* v0, int power, const double* u,
+                       double* rhs, void* stream);
+
 /* Number of tiles a BSSN_MIXED evaluation of u runs in FP64 (tiles whose
  * minimum lapse over their points is below params->fp64_alpha_threshold)
  * and the total number of tiles.  Tiles are those of the kernel a stage on

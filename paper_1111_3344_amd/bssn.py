@@ -102,6 +102,9 @@ def lib():
                                        ctypes.c_double, vp, vp]
         L.bssn_mixed_tile_count.argtypes = [g, p, vp, P(ctypes.c_int64),
                                             P(ctypes.c_int64), vp]
+        L.bssn_radiative_rhs.argtypes = [g, P(ctypes.c_double),
+                                         P(ctypes.c_double), ctypes.c_int,
+                                         vp, vp, vp]
         if hasattr(L, "batch_patches_plan"):
             L.batch_patches_plan.argtypes = [
                 ctypes.c_int, P(bssn_grid), p, P(vp), P(vp), P(vp), P(vp),
@@ -214,6 +217,26 @@ def bssn_mixed_tile_count(grid, params, u, stream=None):
         ctypes.byref(c_grid(grid)), ctypes.byref(_params(params)),
         ptr(grid, u), ctypes.byref(a), ctypes.byref(b), _stream(stream)))
     return a.value, b.value
+
+
+# Values at infinity and wave speeds of the radiative boundary, per slot:
+# the flat-space values (1 for the diagonal conformal metric and the lapse,
+# 0 otherwise); speed 1, and sqrt(2) for the lapse and K, which the 1+log
+# condition propagates at sqrt(f alpha) = sqrt(2) near alpha = 1.
+RADIATIVE_X0 = tuple(1.0 if s in (1, 4, 6, 17) else 0.0 for s in range(25))
+RADIATIVE_V0 = tuple(2.0 ** 0.5 if s in (7, 17) else 1.0 for s in range(25))
+
+
+def bssn_radiative_rhs(grid, u, rhs, x0=RADIATIVE_X0, v0=RADIATIVE_V0,
+                       power=2, stream=None):
+    """Radiative outer boundary: fills the ghost layers of rhs (flat
+    state-shaped tensor whose interior holds the interior right-hand side)
+    from the state u."""
+    a = (ctypes.c_double * 25)(*[float(v) for v in x0])
+    b = (ctypes.c_double * 25)(*[float(v) for v in v0])
+    _check(lib().bssn_radiative_rhs(ctypes.byref(c_grid(grid)), a, b,
+                                    int(power), ptr(grid, u), ptr(grid, rhs),
+                                    _stream(stream)))
 
 
 class BatchPlan:

@@ -204,6 +204,59 @@ int rk4_stage(const bssn_grid* grid, const bssn_params* params, int stage,
   return BSSN_OK;
 }
 
+int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
+                       const double* v0, int power, const double* u,
+                       double* rhs, void* stream) {
+  int rc = check_grid(grid, 4);
+  if (rc) return rc;
+  if (grid->bc != BSSN_BC_STATIC)
+    return fail(BSSN_EINVAL, "the radiative boundary needs a static grid "
+                "(its ghost layers are the boundary points)");
+  if (!x0 || !v0) return fail(BSSN_EINVAL, "x0 and v0 must be non-NULL");
+  if (!u || !rhs) return fail(BSSN_EINVAL, "u and rhs must be non-NULL");
+  if (u == rhs) return fail(BSSN_EINVAL, "rhs must not alias u");
+  if (power < 0 || power > 16)
+    return fail(BSSN_EINVAL, "power = %d outside 0..16", power);
+  for (int s = 0; s < BSSN_NSLOT; ++s)
+    if (!std::isfinite(x0[s]) || !std::isfinite(v0[s]) || v0[s] < 0.0)
+      return fail(BSSN_EINVAL, "slot %d: x0 and v0 must be finite, v0 >= 0",
+                  s);
+  // r = 0 at a boundary point would divide by zero: the coordinate origin
+  // must not be one of them
+  bool at[3];
+  bool inside = true;
+  for (int a = 0; a < 3; ++a) {
+    const double j = grid->ghost - grid->origin[a] / grid->h[a];
+    const double jr = std::nearbyint(j);
+    at[a] = std::fabs(j - jr) <= 1e-9 * (1.0 + std::fabs(j)) && jr >= 0 &&
+            jr < grid->n[a] + 2.0 * grid->ghost;
+    inside = inside && jr >= grid->ghost && jr < grid->n[a] + grid->ghost;
+  }
+  if (at[0] && at[1] && at[2] && !inside)
+    return fail(BSSN_EINVAL, "the coordinate origin is a boundary point");
+  RadiativeArgs A{};
+  A.u = u;
+  A.rhs = rhs;
+  for (int a = 0; a < 3; ++a) {
+    A.n[a] = grid->n[a];
+    A.origin[a] = grid->origin[a];
+    A.h[a] = grid->h[a];
+  }
+  A.ghost = grid->ghost;
+  A.sy = grid->sy;
+  A.sz = grid->sz;
+  A.sf = grid->sf;
+  for (int s = 0; s < BSSN_NSLOT; ++s) {
+    A.x0[s] = x0[s];
+    A.v0[s] = v0[s];
+  }
+  A.power = power;
+  hipError_t e = launch_radiative(A, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "bssn_radiative_rhs launch");
+  g_err = "no error";
+  return BSSN_OK;
+}
+
 }  // extern "C"
 
 // ---- workspaces that live until the process ends ---------------------------------

@@ -100,6 +100,25 @@ hipError_t launch_constraints(const ConstraintArgs& A, int order,
                               double* norms, hipStream_t st);
 int constraint_blocks(const ConstraintArgs& A);
 
+// Radiative outer boundary (bssn_radiative_rhs): the right-hand side on the
+// ghost layers of rhs, layer by layer, from the state u and the interior of
+// rhs.
+struct RadiativeArgs {
+  const double* u;
+  double* rhs;
+  int32_t n[3];
+  int32_t ghost;
+  int64_t sy, sz, sf;
+  double origin[3];
+  double h[3];
+  double x0[NSLOT];
+  double v0[NSLOT];
+  int32_t power;
+};
+hipError_t launch_radiative(const RadiativeArgs& A, hipStream_t st);
+// Points of boundary layer `layer` (1 .. ghost) of an interior n.
+int64_t radiative_layer_points(const int n[3], int layer);
+
 // Count of tiles whose minimum lapse is below thr (device counter), over
 // the tiles of the LDS kernel (lds = 1) or of the direct kernel.
 hipError_t launch_tile_count(const Patch& P, double thr, int lds,

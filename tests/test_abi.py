@@ -103,6 +103,39 @@ def test_constraints_validation():
                               None) == B.BSSN_EINVAL
 
 
+def test_radiative_validation():
+    L = B.lib()
+    x0 = (ctypes.c_double * 25)(*([0.0] * 25))
+    v0 = (ctypes.c_double * 25)(*([1.0] * 25))
+
+    def call(g, power=2, u=1, rhs=2, a=x0, b=v0):
+        return L.bssn_radiative_rhs(ctypes.byref(B.c_grid(g)), a, b, power,
+                                    P(u), P(rhs), None)
+
+    g = I.cell_centred(8, -1, 1, 3)
+    assert call(g, u=1, rhs=1) == B.BSSN_EINVAL          # rhs == u
+    assert call(g, u=0) == B.BSSN_EINVAL
+    assert call(g, power=-1) == B.BSSN_EINVAL
+    assert call(g, power=17) == B.BSSN_EINVAL
+    assert call(g, a=None) == B.BSSN_EINVAL
+    bad = (ctypes.c_double * 25)(*([1.0] * 24 + [-1.0]))
+    assert call(g, b=bad) == B.BSSN_EINVAL
+    assert "slot 24" in B.bssn_last_error()
+    nan = (ctypes.c_double * 25)(*([float("nan")] + [0.0] * 24))
+    assert call(g, a=nan) == B.BSSN_EINVAL
+    gp = I.cell_centred(8, -1, 1, 3, I.BC_PERIODIC)
+    assert call(gp) == B.BSSN_EINVAL
+    assert "static" in B.bssn_last_error()
+    # interior point 0 at (2h, 2h, 2h): the coordinate origin is the ghost
+    # point two steps below it on every axis (every case above and this one
+    # is rejected before anything is launched)
+    h = 0.1
+    go = I.GridSpec((6, 6, 6), 3, (h, h, h), (2 * h, 2 * h, 2 * h),
+                    I.BC_STATIC)
+    assert call(go) == B.BSSN_EINVAL
+    assert "origin" in B.bssn_last_error()
+
+
 def test_periodic_grid_must_cover_stencil():
     g = I.GridSpec((2, 8, 8), 3, (0.1,) * 3, (0,) * 3, I.BC_PERIODIC)
     assert _stage(B.c_grid(g), B.Params().c()) == B.BSSN_EINVAL
