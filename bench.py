@@ -105,6 +105,44 @@ def time_gpu(B, torch, g, u_host, prm, dt, steps, warmup):
     return wall, per_stage
 
 
+RADIATIVE_BYTES_PER_POINT = 600  # state of the point, right-hand side of
+                                 # its inward neighbour, its own: 25 x 3 x 8
+
+
+def time_radiative(B, torch, g, u_host, prm, reps=20, warmup=2):
+    """bssn_radiative_rhs on the workload's grid, timed alone: the interior
+    right-hand side comes from one bssn_rhs call, then reps boundary calls
+    (each rewrites the ghost layers from the same interior) between HIP
+    events on the launch stream."""
+    du = torch.from_numpy(u_host).to("cuda")
+    k = torch.zeros_like(du)
+    stream = torch.cuda.current_stream()
+    B.bssn_rhs(g, prm, du, k, stream)
+    for _ in range(warmup):
+        B.bssn_radiative_rhs(g, du, k, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        B.bssn_radiative_rhs(g, du, k, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    npts = 0
+    for layer in range(1, g.ghost + 1):
+        a = [g.n[i] + 2 * layer for i in range(3)]
+        npts += (2 * a[0] * a[1] + 2 * a[0] * (a[2] - 2) +
+                 2 * (a[1] - 2) * (a[2] - 2))
+    gbs = RADIATIVE_BYTES_PER_POINT * npts / (ms * 1e-3) / 1e9
+    del du, k
+    torch.cuda.empty_cache()
+    return {"kernel": "k_radiative (all ghost layers, one launch)",
+            "ms_per_call": round(ms, 4), "boundary_points": npts,
+            "bytes_per_point": RADIATIVE_BYTES_PER_POINT,
+            "achieved_gbs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(name, target_s=15.0):
     """The oracle on the host cores over a bounded sample of the workload:
     a z-slab of the same grid (same data, static ghosts taken from the full
@@ -566,6 +604,9 @@ def main():
                 if kv and t + "avg_launch_us" in kv:
                     out["mixed"][t[6:] + "profiled_avg_launch_us"] = float(
                         kv[t + "avg_launch_us"])
+    if g.bc == 0:  # static grid: its ghost layers as radiative boundary
+        out["radiative_bc"] = time_radiative(B, torch, g, u,
+                                             B.Params(fd_order=order))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -179,8 +179,10 @@ int bssn_constraints(const bssn_grid* grid, const bssn_params* params,
  * with second-order differences (centred, one-sided at the storage edge);
  * the rest of the source decays as r^-power and is carried outward from the
  * inward neighbour q = p - n (n the outward normal of p's face, edge or
- * corner): rhs(p) = S(p) + (r_q/r_p)^power (rhs(q) - S(q)).  Layers are
- * computed innermost first, each from the previous one.
+ * corner): rhs(p) = S(p) + (r_q/r_p)^power (rhs(q) - S(q)), each layer from
+ * the one inside it.  The recursion is evaluated in closed form (it
+ * telescopes to the interior point p clamped into the interior box), so the
+ * result equals the layer-by-layer one up to rounding.
  *   x0, v0  host, 25 values per slot: value at infinity, wave speed (>= 0)
  *   power   0..16 (2: the second-order decay the paper assumes)
  *   u       device state buffer
@@ -188,9 +190,8 @@ int bssn_constraints(const bssn_grid* grid, const bssn_params* params,
  *           right-hand side (e.g. from bssn_rhs) and is read, not written;
  *           on return its ghost layers hold the boundary right-hand side
  * The grid must be BSSN_BC_STATIC with ghost >= 3, rhs != u, and the
- * coordinate origin must not be a ghost point.  Enqueues one launch per
- * ghost layer on `stream`.  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED,
- * BSSN_EHIP. */
+ * coordinate origin must not be a ghost point.  Enqueues one launch on
+ * `stream`.  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED, BSSN_EHIP. */
 int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
                        const double* v0, int power, const double* u,
                        double* rhs, void* stream);

@@ -101,8 +101,7 @@ hipError_t launch_constraints(const ConstraintArgs& A, int order,
 int constraint_blocks(const ConstraintArgs& A);
 
 // Radiative outer boundary (bssn_radiative_rhs): the right-hand side on the
-// ghost layers of rhs, layer by layer, from the state u and the interior of
-// rhs.
+// ghost layers of rhs from the state u and the interior of rhs.
 struct RadiativeArgs {
   const double* u;
   double* rhs;
@@ -116,8 +115,6 @@ struct RadiativeArgs {
   int32_t power;
 };
 hipError_t launch_radiative(const RadiativeArgs& A, hipStream_t st);
-// Points of boundary layer `layer` (1 .. ghost) of an interior n.
-int64_t radiative_layer_points(const int n[3], int layer);
 
 // Count of tiles whose minimum lapse is below thr (device counter), over
 // the tiles of the LDS kernel (lds = 1) or of the direct kernel.

@@ -10,13 +10,10 @@
 // taken to decay as r^-p and is carried outward from the inward neighbour
 // q = p - n (n: the outward normal of the point's face, edge or corner):
 //   rhs(p) = S(p) + (r_q / r_p)^p (rhs(q) - S(q)).
-// Layer k (the points k steps outside the interior box) reads layer k - 1,
-// so the layers are separate launches, innermost first.
-//
-// One thread per (boundary point of the layer, slot): the layer is the
-// surface of the box of the interior grown by k, enumerated face by face
-// (z faces whole, y faces without their z edges, x faces without either).
-// This is a small, memory-bound pass (about 600 bytes per boundary point).
+// Layer k (the points k steps outside the interior box) is defined from
+// layer k - 1; the recursion telescopes to the interior (k_radiative), so
+// one launch computes every layer.  This is a small, memory-bound pass
+// (about 600 bytes per boundary point).
 #include <hip/hip_runtime.h>
 
 #include "bssn_internal.h"
@@ -61,70 +58,70 @@ __device__ __forceinline__ RadPoint rad_wave(const RadiativeArgs& A, int s,
   return p;
 }
 
+// One thread per (boundary point, slot).  The boundary points (all ghost
+// layers) are numbered in three parts, x fastest where rows are whole:
+//   A  the z slabs (k < g or k >= n2 + g): whole planes;
+//   B  in interior planes, the y slabs: whole rows;
+//   C  in interior rows, the g points at each x end.
+// The layer recursion telescopes: following q = p - n from p reaches, after
+// as many steps as p's layer, the interior point `root` (p clamped into the
+// interior box per axis), and the factors multiply to (r_root / r_p)^power:
+//   rhs(p) = S(p) + (r_root / r_p)^power (rhs(root) - S(root)).
 __global__ void __launch_bounds__(256)
-    k_radiative_layer(const RadiativeArgs A, const int layer,
-                      const int64_t npts) {
+    k_radiative(const RadiativeArgs A, const int64_t na, const int64_t nb,
+                const int64_t nc) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
-  if (t >= npts) return;
-  const int ax = A.n[0] + 2 * layer, ay = A.n[1] + 2 * layer,
-            az = A.n[2] + 2 * layer;
-  // position on the layer's shell, in [0, a) per axis
-  int lx, ly, lz;
-  const int64_t fz = int64_t(ax) * ay, fy = int64_t(ax) * (az - 2);
-  if (t < 2 * fz) {
-    const int64_t m = t % fz;
-    lz = t < fz ? 0 : az - 1;
-    lx = int(m % ax);
-    ly = int(m / ax);
-  } else if (t < 2 * fz + 2 * fy) {
-    const int64_t u = t - 2 * fz, m = u % fy;
-    ly = u < fy ? 0 : ay - 1;
-    lx = int(m % ax);
-    lz = 1 + int(m / ax);
-  } else {
-    const int64_t fx = int64_t(ay - 2) * (az - 2);
-    const int64_t u = t - 2 * fz - 2 * fy, m = u % fx;
-    lx = u < fx ? 0 : ax - 1;
-    ly = 1 + int(m % (ay - 2));
-    lz = 1 + int(m / (ay - 2));
-  }
   const int g = A.ghost;
-  const int i = lx - layer + g, j = ly - layer + g, k = lz - layer + g;
-  // outward normal and the inward neighbour
-  const int sx = i < g ? -1 : (i >= A.n[0] + g ? 1 : 0);
-  const int sy = j < g ? -1 : (j >= A.n[1] + g ? 1 : 0);
-  const int sz = k < g ? -1 : (k >= A.n[2] + g ? 1 : 0);
-  const int qi = i - sx, qj = j - sy, qk = k - sz;
+  const int N0 = A.n[0] + 2 * g, N1 = A.n[1] + 2 * g;
+  int i, j, k;
+  if (t < na) {
+    const int64_t plane = t / (int64_t(N0) * N1), m = t % (int64_t(N0) * N1);
+    k = plane < g ? int(plane) : int(plane) - g + A.n[2] + g;
+    j = int(m / N0);
+    i = int(m % N0);
+  } else if (t < na + nb) {
+    const int64_t u = t - na, row = u / N0;
+    i = int(u % N0);
+    const int jr = int(row % (2 * g));
+    k = g + int(row / (2 * g));
+    j = jr < g ? jr : jr - g + A.n[1] + g;
+  } else if (t < na + nb + nc) {
+    const int64_t u = t - na - nb;
+    const int e = int(u % (2 * g));
+    const int64_t row = u / (2 * g);
+    j = g + int(row % A.n[1]);
+    k = g + int(row / A.n[1]);
+    i = e < g ? e : e - g + A.n[0] + g;
+  } else {
+    return;
+  }
+  const int ri = i < g ? g : (i >= A.n[0] + g ? A.n[0] + g - 1 : i);
+  const int rj = j < g ? g : (j >= A.n[1] + g ? A.n[1] + g - 1 : j);
+  const int rk = k < g ? g : (k >= A.n[2] + g ? A.n[2] + g - 1 : k);
   const RadPoint P = rad_wave(A, s, i, j, k);
-  const RadPoint Q = rad_wave(A, s, qi, qj, qk);
+  const RadPoint Q = rad_wave(A, s, ri, rj, rk);
   const double ratio = Q.r / P.r;
   double f = 1.0;
   for (int e = 0; e < A.power; ++e) f *= ratio;
   double* out = A.rhs + int64_t(s) * A.sf;
-  const double rq = out[int64_t(qk) * A.sz + int64_t(qj) * A.sy + qi];
-  out[int64_t(k) * A.sz + int64_t(j) * A.sy + i] = P.S + f * (rq - Q.S);
+  const double rr = out[int64_t(rk) * A.sz + int64_t(rj) * A.sy + ri];
+  out[int64_t(k) * A.sz + int64_t(j) * A.sy + i] = P.S + f * (rr - Q.S);
 }
 
 }  // namespace
 
-int64_t radiative_layer_points(const int n[3], int layer) {
-  const int64_t ax = n[0] + 2 * layer, ay = n[1] + 2 * layer,
-                az = n[2] + 2 * layer;
-  return 2 * ax * ay + 2 * ax * (az - 2) + 2 * (ay - 2) * (az - 2);
-}
-
 hipError_t launch_radiative(const RadiativeArgs& A, hipStream_t st) {
-  for (int layer = 1; layer <= A.ghost; ++layer) {
-    const int64_t npts = radiative_layer_points(A.n, layer);
-    const int64_t nb = (npts + 255) / 256;
-    if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_radiative_layer, dim3(unsigned(nb), NSLOT),
-                       dim3(256), 0, st, A, layer, npts);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  const int64_t g = A.ghost;
+  const int64_t N0 = A.n[0] + 2 * g, N1 = A.n[1] + 2 * g;
+  const int64_t na = 2 * g * N1 * N0;
+  const int64_t nb = int64_t(A.n[2]) * 2 * g * N0;
+  const int64_t nc = int64_t(A.n[2]) * A.n[1] * 2 * g;
+  const int64_t blocks = (na + nb + nc + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_radiative, dim3(unsigned(blocks), NSLOT), dim3(256), 0,
+                     st, A, na, nb, nc);
+  return hipGetLastError();
 }
 
 }  // namespace bssn
