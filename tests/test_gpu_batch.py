@@ -285,3 +285,47 @@ def test_batched_mixed_many_fp64_tiles_bitwise(B):
         assert np.array_equal(x, y), f"patch {p} differs"
         assert np.isfinite(x).all()
     plan.destroy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_patches256_batched_equals_per_patch(B, precision):
+    """The benchmark's batched workload at full size (256 patches, 58 M
+    interior points) with its autotuned plan: one batched step equals one
+    step of per-patch launches bitwise on every patch (compared on the
+    device).  The per-patch launches are the single-grid stage kernels,
+    which the parity tests tie to the oracle."""
+    specs = I.patches(256)
+    grids = [g for g, _, _ in specs]
+    u0 = []
+    for g, m, c in specs:                      # host copies one at a time
+        u0.append(torch.from_numpy(I.brill_lindquist(g, (m,), (c,)))
+                  .to("cuda"))
+    u = [t.clone() for t in u0]
+    a = [t.clone() for t in u0]
+    b = [t.clone() for t in u0]
+    acc = [torch.zeros_like(t) for t in u0]
+    prm = B.Params(precision=precision)
+    print(f"[full] patches256 precision={precision}", flush=True)
+    plan = B.batch_patches_plan(grids, prm, u, a, b, acc, 0.03125,
+                                autotune=1)
+
+    def reset():
+        for i in range(len(grids)):
+            u[i].copy_(u0[i])
+            a[i].copy_(u0[i])
+            b[i].copy_(u0[i])
+            acc[i].zero_()
+        torch.cuda.synchronize()
+
+    reset()
+    B.batch_patches(plan, 1)
+    torch.cuda.synchronize()
+    got = [t.clone() for t in u]
+    reset()
+    B.batch_patches_unbatched(plan, 1)
+    torch.cuda.synchronize()
+    for p in range(len(grids)):
+        assert torch.equal(got[p], u[p]), f"patch {p} differs"
+        assert bool(torch.isfinite(got[p]).all())
+        assert not torch.equal(got[p], u0[p])   # the step did something
+    plan.destroy()

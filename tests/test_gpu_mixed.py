@@ -11,6 +11,8 @@ state its error as numbers (printed, run with -s to see them) and bound it:
   * after RK4 steps of two-puncture data the constraint norms of the mixed
     run stay within 2x of the FP64 run's.
 """
+import itertools
+
 import numpy as np
 import pytest
 
@@ -25,6 +27,7 @@ pytestmark = pytest.mark.gpu
 # error of a few 1e-6 is expected (measured: at most 1.5e-6 over these
 # cases); per-slot cancellation between terms can raise it further.
 MIXED_RHS_TOL = 1e-5
+EPS = np.finfo(np.float64).eps
 
 
 @pytest.fixture(scope="module")
@@ -216,3 +219,66 @@ def test_split_tiles_take_their_precision(B, case):
         assert np.all(np.abs(a - b).max(1) / D <= MIXED_RHS_TOL)
     if case != "smooth-one-tile":
         assert 0 < n64 < nt
+
+
+# ---- full-size configurations, the benchmark's launches: sampled points ------
+FULL = {
+    "bl1-128": (lambda: I.cell_centred(128, -8, 8, 3),
+                lambda g: I.brill_lindquist(g, (1.0,), ((0, 0, 0),)), 4),
+    "bl2-384-order8": (lambda: I.cell_centred(384, -24, 24, 5),
+                       lambda g: I.brill_lindquist(g, (0.6, 0.4),
+                                                   ((4, 0, 0), (-4, 0, 0))),
+                       8),
+}
+
+
+@pytest.mark.parametrize("case", list(FULL))
+def test_full_size_mixed_stage0_sampled(B, case):
+    """Mixed stage 0 at the benchmark size (the two launches the benchmark
+    times): at sampled points within MIXED_RHS_TOL of the oracle, and at
+    the FP64 tolerance where the point's tile is routed to FP64 (points
+    next to the punctures are sampled)."""
+    gfn, dfn, order = FULL[case]
+    g = gfn()
+    u = dfn(g)
+    print(f"[full-mixed] {case} n={g.n}", flush=True)
+    prm = B.Params(fd_order=order, precision=1)
+    dt = 0.03125
+    du = B.to_device(u)
+    acc = torch.zeros_like(du)
+    out = du.clone()
+    B.rk4_stage(g, prm, 0, dt, du, du, acc, out)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    pts = np.stack([rng.integers(0, g.n[a], size=300) for a in range(3)], 1)
+    # points in the FP64 tiles: around each puncture
+    h = g.h[0]
+    for c in ([0, 0, 0],) if case == "bl1-128" else ([4, 0, 0], [-4, 0, 0]):
+        ic = [int((c[a] - g.origin[a]) / h) for a in range(3)]
+        for d in itertools.product((-2, 0, 1), repeat=3):
+            pts = np.concatenate([pts, [[ic[a] + d[a] for a in range(3)]]])
+    pts = pts.astype(np.int32)
+    k = O.rhs_points(g, O.params(fd_order=order), u, pts)     # (N, 25)
+    idx = (g.off0 + np.arange(25)[None, :] * g.sf
+           + (pts[:, 2:3] + g.ghost) * g.sz + (pts[:, 1:2] + g.ghost) * g.sy
+           + (pts[:, 0:1] + g.ghost))
+    it = torch.from_numpy(idx.reshape(-1)).to(out.device)
+    gout = out[it].cpu().numpy().reshape(idx.shape)
+    del du, acc, out
+    kg = (gout - u[idx]) / (dt / 2)          # the kernel's k at the samples
+    D = np.abs(k).max(0)
+    D = np.where(D > 0, D, D.max())
+    err = np.abs(kg - k) / D                 # (N, 25)
+    assert np.all(err <= MIXED_RHS_TOL), err.max()
+    # routing: tiles (16 x 4 x 4) whose minimum lapse is below 0.3
+    al = g.interior(u)[I.ALP]
+    tmin = _tile_min(al)
+    f64 = tmin[pts[:, 2] // 4, pts[:, 1] // 4, pts[:, 0] // 16] < 0.3
+    print(f"[full-mixed] {case}: {int(f64.sum())} of {len(pts)} samples in "
+          f"FP64 tiles, max error {err.max():.2e} (FP32), "
+          f"{err[f64].max() if f64.any() else 0:.2e} (FP64)", flush=True)
+    assert f64.sum() >= 8
+    # FP64 tiles: the FP64 method, to its tolerance (k is recovered from
+    # out = u + dt/2 k, which costs a few ulps of u / (dt/2))
+    tol = 1e-12 + 8 * EPS * np.abs(u[idx]).max(0) / (dt / 2) / D
+    assert np.all(err[f64] <= tol), err[f64].max()
