@@ -143,6 +143,51 @@ def time_radiative(B, torch, g, u_host, prm, reps=20, warmup=2):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+ADM_BYTES_PER_POINT = 328  # 16 ADM values in, 25 BSSN values out (8 B each)
+
+
+def time_from_adm(B, torch, g, masses, centres, order, reps=5):
+    """bssn_from_adm on the workload's grid and its Brill-Lindquist data in
+    ADM form (g_ij = psi^4 delta_ij, K_ij = 0, pre-collapsed lapse), timed
+    between HIP events on the launch stream over reps calls."""
+    import numpy as np
+    X, Y, Z = g.mesh()
+    psi = np.ones_like(X)
+    for m, c in zip(masses, centres):
+        r = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)
+        psi += m / (2.0 * np.maximum(r, 0.5 * min(g.h)))
+    adm = torch.zeros(g.off0 + 16 * g.sf, dtype=torch.float64)
+    v = g.view(adm.numpy(), 16)
+    for s in (0, 3, 5):
+        v[s] = psi ** 4
+    v[12] = psi ** -2
+    del X, Y, Z, psi
+    dadm = adm.to("cuda")
+    du = torch.empty(g.total, dtype=torch.float64, device="cuda")
+    prm = B.Params(fd_order=order)
+    stream = torch.cuda.current_stream()
+    B.bssn_from_adm(g, prm, dadm, du, stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        B.bssn_from_adm(g, prm, dadm, du, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    npts = 1
+    for a in range(3):
+        npts *= g.n[a] + 2 * g.ghost
+    gbs = ADM_BYTES_PER_POINT * npts / (ms * 1e-3) / 1e9
+    del dadm, du
+    torch.cuda.empty_cache()
+    return {"kernels": "k_adm_point, k_adm_gamma, k_adm_extrap (per layer)",
+            "ms_per_call": round(ms, 4), "storage_points": npts,
+            "bytes_per_point": ADM_BYTES_PER_POINT,
+            "achieved_gbs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(name, target_s=15.0):
     """The oracle on the host cores over a bounded sample of the workload:
     a z-slab of the same grid (same data, static ghosts taken from the full
@@ -607,6 +652,10 @@ def main():
     if g.bc == 0:  # static grid: its ghost layers as radiative boundary
         out["radiative_bc"] = time_radiative(B, torch, g, u,
                                              B.Params(fd_order=order))
+        wl = WORKLOADS[args.workload]
+        if g.npoints <= 256 ** 3:  # initial conversion of the same data
+            out["adm_to_bssn"] = time_from_adm(B, torch, g, wl[4], wl[5],
+                                               order)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -170,6 +170,27 @@ int bssn_constraints(const bssn_grid* grid, const bssn_params* params,
                      const double* centres, int ncent, double r_exc,
                      double* norms, void* stream);
 
+/* Initial conversion from the ADM variables to the BSSN state (section
+ * "Spacetime Curvature Evolution", initial conditions): by the definitions
+ *   phi = ln(det g)/12, gt_ij = e^{-4 phi} g_ij, K = g^ij K_ij,
+ *   At_ij = e^{-4 phi}(K_ij - g_ij K/3), alpha, beta^i copied, B^i = 0,
+ *   slot 24 (A) = 0,
+ * at every storage point; Gt^i = gt^ij gt^kl Gt_jkl from centred differences
+ * (order params->fd_order) of the converted metric at interior points, and on
+ * the ghost layers, innermost first, by the cubic extrapolation
+ *   X(p) = 4X(p-n) - 6X(p-2n) + 4X(p-3n) - X(p-4n)
+ * along n, the outward normal of p's face, or the sum of the face normals at
+ * an edge or corner (e.g. (1,1,0)).
+ *   adm  device, 16 slots in the state layout (slot stride sf):
+ *        g_xx g_xy g_xz g_yy g_yz g_zz, K_xx .. K_zz, alpha, beta^x..beta^z,
+ *        at every storage point (det g > 0)
+ *   u    device state buffer, written at every storage point
+ * Needs n >= 4 on every axis (the extrapolation reaches 4 points inward) and
+ * u != adm.  Enqueues 2 + ghost launches on `stream`.  Errors: BSSN_EINVAL,
+ * BSSN_EUNSUPPORTED, BSSN_EHIP. */
+int bssn_from_adm(const bssn_grid* grid, const bssn_params* params,
+                  const double* adm, double* u, void* stream);
+
 /* Radiative (Sommerfeld-type) outer boundary (section "Spacetime Curvature
  * Evolution", boundary conditions): the right-hand side on the ghost layers
  * of a static grid, which then become evolved boundary points.  Every

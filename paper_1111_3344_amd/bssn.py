@@ -102,6 +102,7 @@ def lib():
                                        ctypes.c_double, vp, vp]
         L.bssn_mixed_tile_count.argtypes = [g, p, vp, P(ctypes.c_int64),
                                             P(ctypes.c_int64), vp]
+        L.bssn_from_adm.argtypes = [g, p, vp, vp, vp]
         L.bssn_radiative_rhs.argtypes = [g, P(ctypes.c_double),
                                          P(ctypes.c_double), ctypes.c_int,
                                          vp, vp, vp]
@@ -217,6 +218,14 @@ def bssn_mixed_tile_count(grid, params, u, stream=None):
         ctypes.byref(c_grid(grid)), ctypes.byref(_params(params)),
         ptr(grid, u), ctypes.byref(a), ctypes.byref(b), _stream(stream)))
     return a.value, b.value
+
+
+def bssn_from_adm(grid, params, adm, u, stream=None):
+    """BSSN state u (flat state-shaped tensor) from the ADM variables adm
+    (flat tensor of off0 + 16 sf elements: g_ij, K_ij, alpha, beta^i)."""
+    _check(lib().bssn_from_adm(ctypes.byref(c_grid(grid)),
+                               ctypes.byref(_params(params)), ptr(grid, adm),
+                               ptr(grid, u), _stream(stream)))
 
 
 # Values at infinity and wave speeds of the radiative boundary, per slot:

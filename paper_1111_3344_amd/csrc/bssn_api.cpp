@@ -204,6 +204,36 @@ int rk4_stage(const bssn_grid* grid, const bssn_params* params, int stage,
   return BSSN_OK;
 }
 
+int bssn_from_adm(const bssn_grid* grid, const bssn_params* params,
+                  const double* adm, double* u, void* stream) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  if ((rc = check_grid(grid, params->fd_order))) return rc;
+  for (int a = 0; a < 3; ++a)
+    if (grid->n[a] < 4)
+      return fail(BSSN_EINVAL, "grid.n[%d] = %d < 4: the cubic extrapolation "
+                  "of the ghost layers reaches 4 points inward", a,
+                  grid->n[a]);
+  if (!adm || !u) return fail(BSSN_EINVAL, "adm and u must be non-NULL");
+  if (adm == u) return fail(BSSN_EINVAL, "u must not alias adm");
+  AdmArgs A{};
+  A.adm = adm;
+  A.u = u;
+  for (int a = 0; a < 3; ++a) {
+    A.n[a] = grid->n[a];
+    A.h[a] = grid->h[a];
+  }
+  A.ghost = grid->ghost;
+  A.sy = grid->sy;
+  A.sz = grid->sz;
+  A.sf = grid->sf;
+  A.order = params->fd_order;
+  hipError_t e = launch_from_adm(A, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "bssn_from_adm launch");
+  g_err = "no error";
+  return BSSN_OK;
+}
+
 int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
                        const double* v0, int power, const double* u,
                        double* rhs, void* stream) {

@@ -116,6 +116,20 @@ struct RadiativeArgs {
 };
 hipError_t launch_radiative(const RadiativeArgs& A, hipStream_t st);
 
+// ADM -> BSSN initial conversion (bssn_from_adm): adm holds 16 slots in
+// the state layout (g_ij, K_ij, alpha, beta^i); every slot of u is written
+// at every storage point.
+struct AdmArgs {
+  const double* adm;
+  double* u;
+  int32_t n[3];
+  int32_t ghost;
+  int64_t sy, sz, sf;
+  double h[3];
+  int32_t order;
+};
+hipError_t launch_from_adm(const AdmArgs& A, hipStream_t st);
+
 // Count of tiles whose minimum lapse is below thr (device counter), over
 // the tiles of the LDS kernel (lds = 1) or of the direct kernel.
 hipError_t launch_tile_count(const Patch& P, double thr, int lds,

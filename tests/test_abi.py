@@ -136,6 +136,23 @@ def test_radiative_validation():
     assert "origin" in B.bssn_last_error()
 
 
+def test_from_adm_validation():
+    L = B.lib()
+    prm = B.Params().c()
+
+    def call(g, prm=prm, adm=1, u=2):
+        return L.bssn_from_adm(ctypes.byref(B.c_grid(g)), ctypes.byref(prm),
+                               P(adm), P(u), None)
+
+    g = I.cell_centred(8, -1, 1, 3)
+    assert call(g, adm=1, u=1) == B.BSSN_EINVAL
+    assert call(g, adm=0) == B.BSSN_EINVAL
+    assert call(g, prm=B.Params(fd_order=8).c()) == B.BSSN_EINVAL  # ghost 3
+    thin = I.GridSpec((8, 3, 8), 3, (0.1,) * 3, (0.0,) * 3, I.BC_STATIC)
+    assert call(thin) == B.BSSN_EINVAL
+    assert "n[1]" in B.bssn_last_error()
+
+
 def test_periodic_grid_must_cover_stencil():
     g = I.GridSpec((2, 8, 8), 3, (0.1,) * 3, (0,) * 3, I.BC_PERIODIC)
     assert _stage(B.c_grid(g), B.Params().c()) == B.BSSN_EINVAL
