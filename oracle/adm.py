@@ -142,3 +142,56 @@ def from_adm(grid, adm, order=4):
     v[GAMX:GAMX + 3, gc:-gc, gc:-gc, gc:-gc] = G
     extrapolate_layers(grid, v[GAMX:GAMX + 3])
     return out
+
+
+# ---- puncture tracking ----------------------------------------------------
+# It follows the object-tracking subsection of the paper's analysis
+# section: a puncture moves with dx^i/dt = -beta^i, the shift interpolated
+# to its position, integrated with one first-order Euler step per call.
+# Reading: the interpolation is tricubic Lagrange on the 4 x 4 x 4 storage
+# points around the position (base node floor((x - x_0)/h) - 1 per axis,
+# x_0 the coordinate of storage index 0), the block shifted inward where it
+# would leave the storage grid.
+def lagrange4(t):
+    """Weights of the cubic through nodes 0, 1, 2, 3 at parameter t."""
+    w = []
+    for m in range(4):
+        p = 1.0
+        for l in range(4):
+            if l != m:
+                p *= (t - l) / (m - l)
+        w.append(p)
+    return w
+
+
+def shift_at(grid, u, pos):
+    """beta^i at each position (array (n, 3)) by tricubic interpolation."""
+    v = grid.view(u)
+    out = []
+    for x in np.asarray(pos, float):
+        base, wts = [], []
+        for a in range(3):
+            N = grid.n[a] + 2 * grid.ghost
+            x0 = grid.origin[a] - grid.ghost * grid.h[a]
+            s = (x[a] - x0) / grid.h[a]
+            b = int(np.floor(s)) - 1
+            b = min(max(b, 0), N - 4)
+            base.append(b)
+            wts.append(lagrange4(s - b))
+        beta = []
+        for c in range(3):
+            f = v[BETX + c]
+            acc = 0.0
+            for k in range(4):
+                for j in range(4):
+                    for i in range(4):
+                        acc += (wts[2][k] * wts[1][j] * wts[0][i] *
+                                f[base[2] + k, base[1] + j, base[0] + i])
+            beta.append(acc)
+        out.append(beta)
+    return np.array(out)
+
+
+def track_punctures(grid, u, pos, dt):
+    """One Euler step of dx/dt = -beta(x) for every position."""
+    return np.asarray(pos, float) - dt * shift_at(grid, u, pos)

@@ -9,7 +9,11 @@ the definitions fix, on the CPU:
     converges to it at fourth order;
   * the cubic extrapolation of the ghost layers reproduces a cubic
     polynomial exactly (faces, edges, corners), and takes the edge normal
-    (1, 1, 0) (a hand-computed value).
+    (1, 1, 0) (a hand-computed value);
+  * puncture tracking: the tricubic interpolation is exact for a shift
+    that is a cubic in each coordinate (inside, near the edge, in the
+    ghosts) and returns the node value at a node; a constant shift moves a
+    puncture by exactly -beta dt.
 """
 import numpy as np
 
@@ -155,3 +159,47 @@ def test_cubic_extrapolation():
     vals = [f[0, z, ey - m, ex - m] for m in range(1, 5)]
     want = 4 * vals[0] - 6 * vals[1] + 4 * vals[2] - vals[3]
     assert f[0, z, ey, ex] == want
+
+
+def _shift_grid():
+    return I.GridSpec((9, 8, 10), 3, (0.2, 0.15, 0.25), (-0.9, -0.5, -1.1),
+                      I.BC_STATIC)
+
+
+def test_tracker_exact_for_tricubic_shift():
+    g = _shift_grid()
+    X, Y, Z = g.mesh()
+
+    def beta(x, y, z):
+        return np.array([0.3 - 0.2 * x ** 3 + 0.5 * x * y * z,
+                         0.1 * y ** 2 * z - 0.4 * x * y ** 3,
+                         -0.2 + 0.6 * x ** 2 * y * z ** 3])
+    u = g.empty()
+    v = g.view(u)
+    b = beta(X, Y, Z)
+    for c in range(3):
+        v[A.BETX + c] = b[c]
+    pos = np.array([[0.13, 0.21, -0.37], [-0.5, 0.02, 0.6],
+                    [0.9, 0.6, 1.0],          # near the far edge
+                    [-1.4, -0.9, -1.6]])      # in the ghost region
+    dt = 0.05
+    new = A.track_punctures(g, u, pos, dt)
+    want = pos - dt * np.stack([beta(*p) for p in pos])
+    assert np.allclose(new, want, rtol=1e-13, atol=1e-14)
+
+
+def test_tracker_at_a_grid_point_and_constant_shift():
+    g = _shift_grid()
+    u = g.empty()
+    v = g.view(u)
+    rng = np.random.default_rng(9)
+    v[A.BETX:A.BETX + 3] = rng.normal(size=v[A.BETX:A.BETX + 3].shape)
+    # storage point (4, 5, 6): its own value exactly (weights 0, 1, 0, 0)
+    x = [g.origin[a] + ((4, 5, 6)[a] - g.ghost) * g.h[a] for a in range(3)]
+    b = A.shift_at(g, u, [x])[0]
+    assert np.allclose(b, v[A.BETX:A.BETX + 3, 6, 5, 4], rtol=1e-14,
+                       atol=1e-15)
+    v[A.BETX:A.BETX + 3] = np.array([0.3, -0.2, 0.1]).reshape(3, 1, 1, 1)
+    new = A.track_punctures(g, u, [[0.05, -0.07, 0.11]], 0.5)
+    assert np.allclose(new, [[0.05 - 0.15, -0.07 + 0.1, 0.11 - 0.05]],
+                       rtol=0, atol=1e-15)
