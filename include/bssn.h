@@ -191,6 +191,22 @@ int bssn_constraints(const bssn_grid* grid, const bssn_params* params,
 int bssn_from_adm(const bssn_grid* grid, const bssn_params* params,
                   const double* adm, double* u, void* stream);
 
+/* Puncture tracking (section "Analysis", object tracking): one first-order
+ * Euler step of dx^i/dt = -beta^i per puncture, the shift of u interpolated
+ * to the position by tricubic Lagrange interpolation on the 4 x 4 x 4
+ * storage points around it (base node floor((x - x_0)/h) - 1 per axis, x_0
+ * the coordinate of storage index 0; the block is shifted inward where it
+ * would leave the storage grid, so positions near or beyond the edge are
+ * extrapolated, never read outside).
+ *   u       device state buffer
+ *   pos     device, 3*npunct coordinates (x, y, z per puncture), updated in
+ *           place: pos <- pos - dt beta(pos)
+ *   npunct  1..65536
+ * Enqueues one launch on `stream`.  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED,
+ * BSSN_EHIP. */
+int bssn_track_punctures(const bssn_grid* grid, const double* u, int npunct,
+                         double* pos, double dt, void* stream);
+
 /* Radiative (Sommerfeld-type) outer boundary (section "Spacetime Curvature
  * Evolution", boundary conditions): the right-hand side on the ghost layers
  * of a static grid, which then become evolved boundary points.  Every

@@ -103,6 +103,8 @@ def lib():
         L.bssn_mixed_tile_count.argtypes = [g, p, vp, P(ctypes.c_int64),
                                             P(ctypes.c_int64), vp]
         L.bssn_from_adm.argtypes = [g, p, vp, vp, vp]
+        L.bssn_track_punctures.argtypes = [g, vp, ctypes.c_int, vp,
+                                           ctypes.c_double, vp]
         L.bssn_radiative_rhs.argtypes = [g, P(ctypes.c_double),
                                          P(ctypes.c_double), ctypes.c_int,
                                          vp, vp, vp]
@@ -226,6 +228,16 @@ def bssn_from_adm(grid, params, adm, u, stream=None):
     _check(lib().bssn_from_adm(ctypes.byref(c_grid(grid)),
                                ctypes.byref(_params(params)), ptr(grid, adm),
                                ptr(grid, u), _stream(stream)))
+
+
+def bssn_track_punctures(grid, u, pos, dt, stream=None):
+    """One Euler step of dx/dt = -beta(x) for the punctures in pos (device
+    float64 tensor of shape (n, 3), updated in place)."""
+    if pos.dtype.itemsize != 8 or pos.numel() % 3 or not pos.is_contiguous():
+        raise TypeError("pos must be a contiguous float64 (n, 3) tensor")
+    _check(lib().bssn_track_punctures(
+        ctypes.byref(c_grid(grid)), ptr(grid, u), pos.numel() // 3,
+        ctypes.c_void_p(pos.data_ptr()), float(dt), _stream(stream)))
 
 
 # Values at infinity and wave speeds of the radiative boundary, per slot:

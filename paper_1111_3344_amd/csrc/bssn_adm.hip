@@ -182,7 +182,62 @@ __global__ void __launch_bounds__(256)
          v[p - 4 * step];
 }
 
+// One Euler step of dx/dt = -beta(x) per puncture (object tracking in the
+// paper's analysis section), beta by tricubic Lagrange interpolation on the
+// 4 x 4 x 4 storage points around x (base node floor((x - x_0)/h) - 1, x_0
+// the coordinate of storage index 0, shifted inward to stay in the grid).
+__global__ void __launch_bounds__(64)
+    k_track(const TrackArgs A, double* __restrict__ pos, const int np,
+            const double dt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int g = A.ghost;
+  double x[3], w[3][4];
+  int b[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    x[a] = pos[3 * p + a];
+    const int N = A.n[a] + 2 * g;
+    const double s = (x[a] - (A.origin[a] - g * A.h[a])) / A.h[a];
+    double fs = floor(s);
+    if (!(fs >= -2.0)) fs = -2.0;  // also NaN
+    if (fs > double(N)) fs = double(N);
+    int bb = int(fs) - 1;
+    bb = bb < 0 ? 0 : (bb > N - 4 ? N - 4 : bb);
+    b[a] = bb;
+    const double t = s - bb;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      double q = 1.0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l)
+        if (l != m) q *= (t - l) / double(m - l);
+      w[a][m] = q;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double* f = A.u + (BETX + c) * A.sf;
+    double acc = 0.0;
+    for (int k = 0; k < 4; ++k)
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc += w[2][k] * w[1][j] * w[0][i] *
+                 f[int64_t(b[2] + k) * A.sz + int64_t(b[1] + j) * A.sy +
+                   (b[0] + i)];
+    pos[3 * p + c] = x[c] - dt * acc;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_track(const TrackArgs& A, double* pos, int np, double dt,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_track, dim3((np + 63) / 64), dim3(64), 0, st, A, pos,
+                     np, dt);
+  return hipGetLastError();
+}
 
 hipError_t launch_from_adm(const AdmArgs& A, hipStream_t st) {
   const int g = A.ghost;

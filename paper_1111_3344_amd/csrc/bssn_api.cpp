@@ -234,6 +234,31 @@ int bssn_from_adm(const bssn_grid* grid, const bssn_params* params,
   return BSSN_OK;
 }
 
+int bssn_track_punctures(const bssn_grid* grid, const double* u, int npunct,
+                         double* pos, double dt, void* stream) {
+  int rc = check_grid(grid, 4);
+  if (rc) return rc;
+  if (!u || !pos) return fail(BSSN_EINVAL, "u and pos must be non-NULL");
+  if (npunct < 1 || npunct > 65536)
+    return fail(BSSN_EINVAL, "npunct = %d outside 1..65536", npunct);
+  if (!std::isfinite(dt)) return fail(BSSN_EINVAL, "dt is not finite");
+  TrackArgs A{};
+  A.u = u;
+  for (int a = 0; a < 3; ++a) {
+    A.n[a] = grid->n[a];
+    A.origin[a] = grid->origin[a];
+    A.h[a] = grid->h[a];
+  }
+  A.ghost = grid->ghost;
+  A.sy = grid->sy;
+  A.sz = grid->sz;
+  A.sf = grid->sf;
+  hipError_t e = launch_track(A, pos, npunct, dt, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "bssn_track_punctures launch");
+  g_err = "no error";
+  return BSSN_OK;
+}
+
 int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
                        const double* v0, int power, const double* u,
                        double* rhs, void* stream) {

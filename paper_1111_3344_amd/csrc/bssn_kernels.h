@@ -130,6 +130,19 @@ struct AdmArgs {
 };
 hipError_t launch_from_adm(const AdmArgs& A, hipStream_t st);
 
+// Puncture tracking (bssn_track_punctures): the state's shift at each
+// position (tricubic), one Euler step of dx/dt = -beta.
+struct TrackArgs {
+  const double* u;
+  int32_t n[3];
+  int32_t ghost;
+  int64_t sy, sz, sf;
+  double origin[3];
+  double h[3];
+};
+hipError_t launch_track(const TrackArgs& A, double* pos, int np, double dt,
+                        hipStream_t st);
+
 // Count of tiles whose minimum lapse is below thr (device counter), over
 // the tiles of the LDS kernel (lds = 1) or of the direct kernel.
 hipError_t launch_tile_count(const Patch& P, double thr, int lds,

@@ -153,6 +153,21 @@ def test_from_adm_validation():
     assert "n[1]" in B.bssn_last_error()
 
 
+def test_track_punctures_validation():
+    L = B.lib()
+    g = I.cell_centred(8, -1, 1, 3)
+
+    def call(n=2, u=1, pos=2, dt=0.1):
+        return L.bssn_track_punctures(ctypes.byref(B.c_grid(g)), P(u), n,
+                                      P(pos), dt, None)
+
+    assert call(n=0) == B.BSSN_EINVAL
+    assert call(n=65537) == B.BSSN_EINVAL
+    assert call(u=0) == B.BSSN_EINVAL
+    assert call(pos=0) == B.BSSN_EINVAL
+    assert call(dt=float("nan")) == B.BSSN_EINVAL
+
+
 def test_periodic_grid_must_cover_stencil():
     g = I.GridSpec((2, 8, 8), 3, (0.1,) * 3, (0,) * 3, I.BC_PERIODIC)
     assert _stage(B.c_grid(g), B.Params().c()) == B.BSSN_EINVAL

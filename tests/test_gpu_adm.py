@@ -112,3 +112,24 @@ def test_brill_lindquist_adm_gives_the_bssn_data(B):
     other = [s for s in range(25) if s not in gam]
     assert np.all(err[other] <= 1e-12), (err[other].max(),)
     assert np.all(err[gam] <= 1e-9), (err[gam].max(),)
+
+
+def test_track_punctures_matches_oracle(B):
+    g = I.GridSpec((21, 18, 25), 3, (0.2, 0.15, 0.25), (-2.1, -1.3, -3.0),
+                   I.BC_STATIC)
+    u = I.smooth_random(g, seed=41)
+    rng = np.random.default_rng(8)
+    lo = np.array([g.origin[a] - g.ghost * g.h[a] for a in range(3)])
+    hi = np.array([g.origin[a] + (g.n[a] + g.ghost - 1) * g.h[a]
+                   for a in range(3)])
+    pos = rng.uniform(lo - 0.3, hi + 0.3, size=(50, 3))   # some outside
+    pos[0] = [g.origin[a] + 4 * g.h[a] for a in range(3)]  # on a node
+    dt = 0.07
+    want = A.track_punctures(g, u, pos, dt)
+    dpos = torch.from_numpy(pos.copy()).to("cuda")
+    B.bssn_track_punctures(g, B.to_device(u), dpos, dt)
+    torch.cuda.synchronize()
+    got = dpos.cpu().numpy()
+    step = np.abs(want - pos).max()
+    assert np.abs(got - want).max() <= 1e-13 * max(1.0, np.abs(pos).max())
+    assert step > 0
