@@ -7,6 +7,9 @@ ghost layer k to 1e-12 * 15^(k-1), the growth bound of the layered cubic
 extrapolation;
 Brill-Lindquist ADM data must give the closed-form BSSN state that the
 input module builds directly (phi = ln psi, conformally flat, Gt = 0).
+Puncture tracking (bssn_track_punctures) must move positions inside, near
+and beyond the edge of the storage grid as the oracle does, to 1e-13 of the
+coordinates' size.
 """
 import numpy as np
 import pytest
