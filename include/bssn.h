@@ -306,6 +306,79 @@ int batch_patches_launch_mode(const bssn_batch_plan* plan);
 /* Release the plan (its graph, work list and device copies). */
 int batch_patches_destroy(bssn_batch_plan* plan);
 
+/* ---- refinement hierarchy glue (the framework section's mesh refinement:
+ * Berger-Oliger stepping with subcycling; fine-grid boundaries filled by
+ * interpolation in space and time from the coarser level; the fine
+ * solution put back into the coarse grid where they overlap) ----------- */
+typedef struct bssn_amr_plan bssn_amr_plan;
+
+typedef struct {
+  int32_t level;      /* 0 = coarsest; level L has half the spacing of L-1 */
+  bssn_grid grid;     /* the patch's grid (bc must be BSSN_BC_STATIC)       */
+} bssn_amr_patch;
+
+/* Plan the glue of a hierarchy of npatch (1..65536) cell-centred patches
+ * (host array).  Every level up to the highest must hold a patch; the
+ * patches of one level share its spacing and lattice (origins an integer
+ * number of spacings apart), and a level's points lie a quarter coarse
+ * spacing from the coarser level's points (fine cells split coarse cells
+ * in eight).  For every ghost point of a patch on level L >= 1 the plan
+ * takes, in this order: a copy from the first other level-L patch (in
+ * list order) whose interior holds the point; else the tricubic
+ * interpolation from the first level-(L-1) patch whose storage grid
+ * (ghosts included) holds the 4 x 4 x 4 coarse block around it (nodes
+ * floor(s) - 1 .. floor(s) + 2 per axis, s the point in coarse index
+ * units; weights (-7, 105, 35, -5)/128 or their mirror).  A ghost point
+ * covered by neither is an error (BSSN_EINVAL, naming the patch and
+ * point).  Restriction: every interior point of a level-(L-1) patch whose
+ * eight children lie in the interior of a level-L patch (the first in list
+ * order) takes the tricubic midpoint interpolation of that patch's storage,
+ * weights (-1, 9, 9, -1)/16 per axis.  Allocates the op lists on the
+ * current device (one op of 32 B per filled ghost point and per restricted
+ * point).  *out receives the plan.  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED,
+ * BSSN_EHIP. */
+int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
+                         bssn_amr_plan** out);
+
+/* Host array counts[3] <- for refined level `level` (1..nlevel-1): the
+ * ghost points filled, how many of them are sibling copies, and the
+ * coarse points restriction writes. */
+int bssn_amr_plan_counts(const bssn_amr_plan* plan, int level,
+                         int64_t* counts);
+
+/* Fill the ghost points of every level-`level` patch (level >= 1), on
+ * `stream`, on the plan's device.
+ *   u_tab     device array of npatch device state pointers (the layout of
+ *             the patch's grid, pointing at element 0 of slot 0); the
+ *             level-`level` entries are written (ghosts only) and read
+ *             (interiors, for sibling copies); other entries are not read
+ *   ntl       1..3 coarse time levels
+ *   src_tabs  host array of ntl device arrays of npatch device state
+ *             pointers: the coarse level's states at times t_src[l] (only
+ *             the level-(level-1) entries are read)
+ *   t_src     host, ntl distinct finite times; t the target time
+ * Prolonged values are the Lagrange interpolation in time through the ntl
+ * levels of the spatial interpolations.  One launch; no allocation.  The
+ * pointer tables must stay valid until the launch has run.  Errors:
+ * BSSN_EINVAL, BSSN_EHIP. */
+int bssn_amr_fill_ghosts(const bssn_amr_plan* plan, int level,
+                         double* const* u_tab, int ntl,
+                         const double* const* const* src_tabs,
+                         const double* t_src, double t, void* stream);
+
+/* Restrict refined level `level` into level - 1, on `stream`:
+ *   fine_tab    device array of npatch device state pointers (level-`level`
+ *               entries read, ghosts included)
+ *   coarse_tab  device array of npatch device state pointers (level-1
+ *               entries: the covered interior points are written)
+ * One launch; no allocation.  Errors: BSSN_EINVAL, BSSN_EHIP. */
+int bssn_amr_restrict(const bssn_amr_plan* plan, int level,
+                      const double* const* fine_tab, double* const* coarse_tab,
+                      void* stream);
+
+/* Release the plan (its device op lists); NULL is accepted. */
+int bssn_amr_plan_destroy(bssn_amr_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

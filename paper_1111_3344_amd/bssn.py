@@ -10,6 +10,7 @@ slots); the pointer handed to the library is the ghost corner of slot 0.
 """
 from __future__ import annotations
 
+import collections
 import ctypes
 import dataclasses
 import math
@@ -44,6 +45,10 @@ class bssn_grid(ctypes.Structure):
                 ("sy", ctypes.c_int64), ("sz", ctypes.c_int64),
                 ("sf", ctypes.c_int64), ("origin", ctypes.c_double * 3),
                 ("h", ctypes.c_double * 3), ("bc", ctypes.c_int32)]
+
+
+class bssn_amr_patch(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("grid", bssn_grid)]
 
 
 class bssn_params(ctypes.Structure):
@@ -105,6 +110,15 @@ def lib():
         L.bssn_from_adm.argtypes = [g, p, vp, vp, vp]
         L.bssn_track_punctures.argtypes = [g, vp, ctypes.c_int, vp,
                                            ctypes.c_double, vp]
+        L.bssn_amr_plan_create.argtypes = [P(bssn_amr_patch), ctypes.c_int,
+                                           P(vp)]
+        L.bssn_amr_plan_counts.argtypes = [vp, ctypes.c_int,
+                                           P(ctypes.c_int64)]
+        L.bssn_amr_fill_ghosts.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int,
+                                           P(vp), P(ctypes.c_double),
+                                           ctypes.c_double, vp]
+        L.bssn_amr_restrict.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.bssn_amr_plan_destroy.argtypes = [vp]
         L.bssn_radiative_rhs.argtypes = [g, P(ctypes.c_double),
                                          P(ctypes.c_double), ctypes.c_int,
                                          vp, vp, vp]
@@ -322,6 +336,69 @@ def batch_patches_destroy(plan):
 
 
 # ---- device buffers -------------------------------------------------------
+class AmrPlan:
+    """Glue plan of a refinement hierarchy: hier is a list of (level, grid)
+    pairs; state lists below are indexed like hier (None where a call does
+    not read the entry)."""
+
+    def __init__(self, hier):
+        import torch
+        self.hier = list(hier)
+        arr = (bssn_amr_patch * len(self.hier))()
+        for i, (lv, g) in enumerate(self.hier):
+            arr[i].level = lv
+            arr[i].grid = c_grid(g)
+        h = ctypes.c_void_p()
+        _check(lib().bssn_amr_plan_create(arr, len(self.hier),
+                                          ctypes.byref(h)))
+        self.h = h
+        self._torch = torch
+        # tables of recent calls: a launch may still be queued when the
+        # next call builds its own
+        self._keep = collections.deque(maxlen=64)
+
+    def _table(self, states):
+        vals = []
+        for (lv, g), t in zip(self.hier, states):
+            vals.append(0 if t is None else ptr(g, t).value)
+        tab = self._torch.tensor(vals, dtype=self._torch.int64,
+                                 device="cuda")
+        self._keep.append(tab)
+        return ctypes.c_void_p(tab.data_ptr())
+
+    def counts(self, level):
+        c = (ctypes.c_int64 * 3)()
+        _check(lib().bssn_amr_plan_counts(self.h, int(level), c))
+        return tuple(c)
+
+    def fill_ghosts(self, level, states, coarse_levels, t_src, t,
+                    stream=None):
+        ut = self._table(states)
+        tabs = (ctypes.c_void_p * len(coarse_levels))(
+            *[self._table(c).value for c in coarse_levels])
+        ts = (ctypes.c_double * len(t_src))(*[float(x) for x in t_src])
+        _check(lib().bssn_amr_fill_ghosts(self.h, int(level), ut,
+                                          len(coarse_levels), tabs, ts,
+                                          float(t), _stream(stream)))
+
+    def restrict(self, level, fine_states, coarse_states, stream=None):
+        _check(lib().bssn_amr_restrict(self.h, int(level),
+                                       self._table(fine_states),
+                                       self._table(coarse_states),
+                                       _stream(stream)))
+
+    def destroy(self):
+        if self.h:
+            lib().bssn_amr_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 def to_device(flat, device="cuda"):
     import torch
     return torch.from_numpy(flat).to(device)

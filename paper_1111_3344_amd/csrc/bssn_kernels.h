@@ -143,6 +143,29 @@ struct TrackArgs {
 hipError_t launch_track(const TrackArgs& A, double* pos, int np, double dt,
                         hipStream_t st);
 
+// Mesh-refinement glue (bssn_amr_*): ops built on the host, one per filled
+// ghost point or restricted coarse point.  dst and src are element offsets
+// from the slot-0 origin of the destination and source patch states.
+enum { AMR_PROLONG = 1 };  // code bit 0; bits 1..3: x, y, z phase (1.75)
+struct AmrOp {
+  int64_t dst, src;
+  int32_t dpatch, spatch;
+  int32_t code, pad;
+};
+struct AmrGeo {
+  int64_t sy, sz, sf;
+};
+struct AmrTime {
+  const double* const* tab[3];  // device tables of coarse state pointers
+  double w[3];                  // Lagrange weights in time
+  int ntl;
+};
+hipError_t launch_amr_fill(const AmrOp* ops, int64_t nops, const AmrGeo* geo,
+                           double* const* u, const AmrTime& T, hipStream_t st);
+hipError_t launch_amr_restrict(const AmrOp* ops, int64_t nops,
+                               const AmrGeo* geo, double* const* coarse,
+                               const double* const* fine, hipStream_t st);
+
 // Count of tiles whose minimum lapse is below thr (device counter), over
 // the tiles of the LDS kernel (lds = 1) or of the direct kernel.
 hipError_t launch_tile_count(const Patch& P, double thr, int lds,

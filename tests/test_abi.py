@@ -168,6 +168,55 @@ def test_track_punctures_validation():
     assert call(dt=float("nan")) == B.BSSN_EINVAL
 
 
+def _amr_create(hier):
+    arr = (B.bssn_amr_patch * len(hier))()
+    for i, (lv, g) in enumerate(hier):
+        arr[i].level = lv
+        arr[i].grid = B.c_grid(g)
+    h = ctypes.c_void_p()
+    rc = B.lib().bssn_amr_plan_create(arr, len(hier), ctypes.byref(h))
+    return rc, h
+
+
+def test_amr_plan_validation():
+    """Hierarchies the plan must refuse, before it allocates anything."""
+    from tests import amr_hier as H
+    L = B.lib()
+    c = I.GridSpec((12, 12, 12), 3, (0.2,) * 3, (0.0, 0.0, 0.0),
+                   I.BC_STATIC)
+    f = H.child(c, (3, 3, 3), (8, 8, 8))
+    h = ctypes.c_void_p()
+    assert L.bssn_amr_plan_create(None, 1, ctypes.byref(h)) == B.BSSN_EINVAL
+    assert _amr_create([])[0] == B.BSSN_EINVAL
+    # a level without patches
+    assert _amr_create([(0, c), (2, f)])[0] == B.BSSN_EINVAL
+    # spacing not half of the coarser level's
+    bad_h = I.GridSpec(f.n, 3, (0.09,) * 3, f.origin, I.BC_STATIC)
+    assert _amr_create([(0, c), (1, bad_h)])[0] == B.BSSN_EINVAL
+    # fine points on the coarse points (vertex-style), not a quarter off
+    bad_o = I.GridSpec(f.n, 3, f.h, (0.6, 0.6, 0.6), I.BC_STATIC)
+    assert _amr_create([(0, c), (1, bad_o)])[0] == B.BSSN_EINVAL
+    # a sibling off its level's lattice
+    off = H.sibling(f, (0, 0, 0))
+    off = I.GridSpec(off.n, 3, off.h, (off.origin[0] + 0.03,) +
+                     off.origin[1:], I.BC_STATIC)
+    assert _amr_create([(0, c), (1, f), (1, off)])[0] == B.BSSN_EINVAL
+    # a fine patch whose ghosts leave the coarse storage
+    out = H.child(c, (-3, 0, 0), (8, 8, 8))
+    rc, _ = _amr_create([(0, c), (1, out)])
+    assert rc == B.BSSN_EINVAL
+    assert "ghost point" in B.bssn_last_error()
+    # periodic patches are refused
+    per = I.GridSpec(c.n, 3, c.h, c.origin, I.BC_PERIODIC)
+    assert _amr_create([(0, per)])[0] == B.BSSN_EINVAL
+    # calls on a NULL plan
+    assert L.bssn_amr_fill_ghosts(None, 1, P(1), 1, None, None, 0.0,
+                                  None) == B.BSSN_EINVAL
+    assert L.bssn_amr_restrict(None, 1, P(1), P(2), None) == B.BSSN_EINVAL
+    assert L.bssn_amr_plan_counts(None, 1, None) == B.BSSN_EINVAL
+    assert L.bssn_amr_plan_destroy(None) == B.BSSN_OK
+
+
 def test_periodic_grid_must_cover_stencil():
     g = I.GridSpec((2, 8, 8), 3, (0.1,) * 3, (0,) * 3, I.BC_PERIODIC)
     assert _stage(B.c_grid(g), B.Params().c()) == B.BSSN_EINVAL
