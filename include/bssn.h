@@ -335,19 +335,23 @@ typedef struct {
  * order) takes the tricubic midpoint interpolation of that patch's storage,
  * weights (-1, 9, 9, -1)/16 per axis.  Allocates the op lists on the
  * current device (one op of 32 B per filled ghost point and per restricted
- * point).  *out receives the plan.  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED,
+ * point; level-0 ghost points inside another level-0 interior are planned
+ * as copies).  *out receives the plan.  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED,
  * BSSN_EHIP. */
 int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
                          bssn_amr_plan** out);
 
-/* Host array counts[3] <- for refined level `level` (1..nlevel-1): the
- * ghost points filled, how many of them are sibling copies, and the
- * coarse points restriction writes. */
+/* Host array counts[3] <- for level `level` (0..nlevel-1): the ghost
+ * points filled, how many of them are sibling copies, and the level-1
+ * points restriction from this level writes (0 for level 0). */
 int bssn_amr_plan_counts(const bssn_amr_plan* plan, int level,
                          int64_t* counts);
 
-/* Fill the ghost points of every level-`level` patch (level >= 1), on
- * `stream`, on the plan's device.
+/* Fill the ghost points of every level-`level` patch, on `stream`, on the
+ * plan's device.  Level 0 exchanges only: a level-0 ghost point inside
+ * another level-0 patch's interior (the first in list order) takes its
+ * value; the other level-0 ghosts (the physical boundary) are left alone,
+ * and ntl, src_tabs, t_src and t are not read.
  *   u_tab     device array of npatch device state pointers (the layout of
  *             the patch's grid, pointing at element 0 of slot 0); the
  *             level-`level` entries are written (ghosts only) and read

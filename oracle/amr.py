@@ -15,6 +15,9 @@ Readings (the paper names neither the orders nor the grid staggering):
   * patches are cell-centred grids (state layout of the main kernels); a
     fine cell is one eighth of a coarse cell, so a fine point lies a
     quarter of a coarse spacing from a coarse point along each axis;
+  * a ghost point of a level-0 patch that lies in another level-0 patch's
+    interior takes that patch's value (the first in list order); the
+    other level-0 ghosts are the physical boundary and are left alone;
   * a ghost point of a patch on level L >= 1 takes, in this order:
       1. the value of the first other patch of level L (in list order)
          whose interior holds the same point (a copy);
@@ -120,7 +123,7 @@ def fill_ghosts(hier, level, states, coarse_states, t_src, t):
                    per patch (those of level - 1 are read)
     t_src, t       the coarse time levels' times and the target time
     """
-    tw = lagrange(t, list(t_src))
+    tw = lagrange(t, list(t_src)) if level > 0 else []
     for p, (lev, grid) in enumerate(hier):
         if lev != level:
             continue
@@ -137,7 +140,7 @@ def fill_ghosts(hier, level, states, coarse_states, t_src, t):
                     dst[:, k, j, i] = src[:, idx[2], idx[1], idx[0]]
                     done = True
                     break
-            if done:
+            if done or level == 0:
                 continue
             for q, (lq, gq) in enumerate(hier):
                 if lq != level - 1:

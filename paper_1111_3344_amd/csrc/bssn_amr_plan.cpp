@@ -135,7 +135,7 @@ int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
   plan.ncopy.assign(nlevel, 0);
   plan.restr_begin.assign(nlevel, 0);
   plan.restr_count.assign(nlevel, 0);
-  for (int L = 1; L < nlevel; ++L) {
+  for (int L = 0; L < nlevel; ++L) {
     plan.fill_begin[L] = int64_t(ops.size());
     for (int p = 0; p < npatch; ++p) {
       const Lat& P = lat[p];
@@ -171,6 +171,7 @@ int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
               found = true;
               ++plan.ncopy[L];
             }
+            if (!found && L == 0) continue;  // physical boundary
             for (int c = 0; c < npatch && !found; ++c) {
               const Lat& C = lat[c];
               if (C.level != L - 1) continue;
@@ -265,8 +266,8 @@ int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
 int bssn_amr_plan_counts(const bssn_amr_plan* plan, int level,
                          int64_t* counts) {
   if (!plan || !counts) return fail(BSSN_EINVAL, "plan or counts is NULL");
-  if (level < 1 || level >= plan->nlevel)
-    return fail(BSSN_EINVAL, "level %d outside 1..%d", level,
+  if (level < 0 || level >= plan->nlevel)
+    return fail(BSSN_EINVAL, "level %d outside 0..%d", level,
                 plan->nlevel - 1);
   counts[0] = plan->fill_count[level];
   counts[1] = plan->ncopy[level];
@@ -274,10 +275,10 @@ int bssn_amr_plan_counts(const bssn_amr_plan* plan, int level,
   return BSSN_OK;
 }
 
-static int check_level_call(const bssn_amr_plan* plan, int level) {
+static int check_level_call(const bssn_amr_plan* plan, int level, int lo) {
   if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
-  if (level < 1 || level >= plan->nlevel)
-    return fail(BSSN_EINVAL, "level %d outside 1..%d", level,
+  if (level < lo || level >= plan->nlevel)
+    return fail(BSSN_EINVAL, "level %d outside %d..%d", level, lo,
                 plan->nlevel - 1);
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
@@ -293,12 +294,22 @@ int bssn_amr_fill_ghosts(const bssn_amr_plan* plan, int level,
                          const double* const* const* src_tabs,
                          const double* t_src, double t, void* stream) {
   if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
-  if (!u_tab || !src_tabs || !t_src)
-    return fail(BSSN_EINVAL, "u_tab, src_tabs and t_src must be non-NULL");
+  if (!u_tab) return fail(BSSN_EINVAL, "u_tab is NULL");
+  AmrTime T{};
+  if (level == 0) {  // sibling exchange only: no coarse level
+    int rc = check_level_call(plan, 0, 0);
+    if (rc) return rc;
+    hipError_t e = launch_amr_fill(plan->d_ops + plan->fill_begin[0],
+                                   plan->fill_count[0], plan->d_geo, u_tab,
+                                   T, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "bssn_amr_fill_ghosts launch");
+    return BSSN_OK;
+  }
+  if (!src_tabs || !t_src)
+    return fail(BSSN_EINVAL, "src_tabs and t_src must be non-NULL");
   if (ntl < 1 || ntl > 3)
     return fail(BSSN_EINVAL, "ntl = %d outside 1..3", ntl);
   if (!std::isfinite(t)) return fail(BSSN_EINVAL, "t is not finite");
-  AmrTime T{};
   T.ntl = ntl;
   for (int l = 0; l < ntl; ++l) {
     if (!src_tabs[l]) return fail(BSSN_EINVAL, "src_tabs[%d] is NULL", l);
@@ -308,7 +319,7 @@ int bssn_amr_fill_ghosts(const bssn_amr_plan* plan, int level,
       if (t_src[m] == t_src[l])
         return fail(BSSN_EINVAL, "t_src[%d] == t_src[%d]", m, l);
   }
-  int rc = check_level_call(plan, level);
+  int rc = check_level_call(plan, level, 1);
   if (rc) return rc;
   // Lagrange weights in time through the coarse time levels
   for (int l = 0; l < ntl; ++l) {
@@ -331,7 +342,7 @@ int bssn_amr_restrict(const bssn_amr_plan* plan, int level,
   if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
   if (!fine_tab || !coarse_tab)
     return fail(BSSN_EINVAL, "fine_tab and coarse_tab must be non-NULL");
-  int rc = check_level_call(plan, level);
+  int rc = check_level_call(plan, level, 1);
   if (rc) return rc;
   hipError_t e = launch_amr_restrict(
       plan->d_ops + plan->restr_begin[level], plan->restr_count[level],

@@ -44,3 +44,15 @@ def three_level(h=0.2, ghost=3):
     f0 = child(c0, (3, 3, 4), (14, 12, 12), ghost)
     ff = child(f0, (3, 2, 3), (10, 12, 10), ghost)
     return [(0, c0), (1, f0), (2, ff)]
+
+
+def bo_level(h=0.2, ghost=3):
+    """Two coarse patches sharing a face (x), two fine siblings sharing a
+    face, the fine region straddling the coarse seam: every kind of ghost
+    source in a small hierarchy for time stepping."""
+    c0 = I.GridSpec((8, 14, 14), ghost, (h, h, h), (-1.3, -1.3, -1.3),
+                    I.BC_STATIC)
+    c1 = sibling(c0, (8, 0, 0), (6, 14, 14))
+    f0 = child(c0, (5, 5, 5), (6, 6, 6), ghost)
+    f1 = sibling(f0, (6, 0, 0))
+    return [(0, c0), (0, c1), (1, f0), (1, f1)]

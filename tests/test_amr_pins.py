@@ -10,6 +10,8 @@
     a line (two levels);
   * a ghost point inside a sibling's interior takes the sibling's value
     (a copy, checked by hand geometry), every other ghost the coarse one;
+    on level 0 the shared face is exchanged and the physical boundary
+    ghosts are left alone;
   * restriction is exact for a tricubic field on the covered coarse points
     and leaves every other point alone;
   * prolongation of a smooth field converges at fourth order;
@@ -141,6 +143,32 @@ def test_sibling_copy_before_prolongation():
     assert cp.sum() == g0.ghost * ny * nz
     got_off = np.abs(v[0] - P[0]) > 50
     assert np.array_equal(got_off & _ghost_mask(g0), cp)
+
+
+def test_level0_sync_copies_and_keeps_the_boundary():
+    hr = H.two_level()
+    rng = np.random.default_rng(12)
+    states = [rng.normal(size=g.total) for _, g in hr]
+    before = [u.copy() for u in states]
+    M.fill_ghosts(hr, 0, states, None, None, 0.0)
+    # c0 (patch 0) and c1 (patch 1) touch at c0's +x face
+    c0, c1 = hr[0][1], hr[1][1]
+    g = c0.ghost
+    v0, v1 = c0.view(states[0]), c1.view(states[1])
+    face = v0[:, g:-g, g:-g, g + c0.n[0]:]
+    assert np.array_equal(face, v1[:, g:-g, g:-g, g:2 * g])
+    face1 = v1[:, g:-g, g:-g, :g]
+    assert np.array_equal(face1, v0[:, g:-g, g:-g, c0.n[0]:c0.n[0] + g])
+    # every other point of the level-0 patches is unchanged, and the fine
+    # patches are not touched
+    m0 = np.zeros(v0.shape[1:], bool)
+    m0[g:-g, g:-g, g + c0.n[0]:] = True
+    assert np.array_equal(v0[:, ~m0], c0.view(before[0])[:, ~m0])
+    m1 = np.zeros(v1.shape[1:], bool)
+    m1[g:-g, g:-g, :g] = True
+    assert np.array_equal(v1[:, ~m1], c1.view(before[1])[:, ~m1])
+    for p in range(2, len(hr)):
+        assert np.array_equal(states[p], before[p])
 
 
 def test_restriction_exact_and_local():
