@@ -188,6 +188,85 @@ def time_from_adm(B, torch, g, masses, centres, order, reps=5):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+AMR_FILL_BYTES = 232      # op (32 B) + 25 values written; coarse reads below
+AMR_RESTRICT_BYTES = 1832  # op (32 B) + 25 values written + 8 children read
+
+
+def time_amr_glue(B, torch, g, reps=10):
+    """Ghost fill and restriction of a three-level hierarchy on the
+    workload's grid: level 0 the grid itself; level 1 and 2 one patch of
+    the same size at half and a quarter of the spacing, centred (cells
+    n/4 .. 3n/4 of the level below).  Three coarse time levels, target
+    time between them.  The state values do not change the work (random
+    device data).  Timed between HIP events on the launch stream; the
+    pointer tables are built before the timed region."""
+    import ctypes
+    from paper_1111_3344_amd import inputs as I
+
+    def child(par):  # fine cells split coarse cells n/4 .. 3n/4 - 1
+        h = tuple(x / 2 for x in par.h)
+        o = tuple(par.origin[a] + (par.n[a] // 4 - 0.25) * par.h[a]
+                  for a in range(3))
+        return I.GridSpec(tuple(par.n), par.ghost, h, o, I.BC_STATIC)
+
+    n = g.n
+    lv1 = child(g)
+    lv2 = child(lv1)
+    hier = [(0, g), (1, lv1), (2, lv2)]
+    plan = B.AmrPlan(hier)
+
+    def state(gr):
+        return torch.randn(gr.total, dtype=torch.float64, device="cuda")
+
+    u = [state(gr) for _, gr in hier]
+    old = [[state(gr) for _, gr in hier] for _ in range(2)]
+    tabs = [plan._table(x) for x in (u, old[0], old[1])]
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    L = B.lib()
+    ts = (ctypes.c_double * 3)(0.0, 1.0, 2.0)
+    src = (ctypes.c_void_p * 3)(tabs[1].value, tabs[2].value, tabs[0].value)
+
+    def fill(level):
+        B._check(L.bssn_amr_fill_ghosts(plan.h, level, tabs[0], 3, src, ts,
+                                        1.25, sp))
+
+    def restrict(level):
+        B._check(L.bssn_amr_restrict(plan.h, level, tabs[0], tabs[0], sp))
+
+    res = {}
+    for name, fn, level in (("fill_level1", fill, 1), ("fill_level2", fill, 2),
+                            ("restrict_level1", restrict, 1),
+                            ("restrict_level2", restrict, 2)):
+        fn(level)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn(level)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nfill, ncopy, nrestr = plan.counts(level)
+        if name.startswith("fill"):
+            nops = nfill
+            # each coarse value serves about 8 fine points (3 time levels)
+            bpo = AMR_FILL_BYTES + 3 * 200 / 8
+        else:
+            nops = nrestr
+            bpo = AMR_RESTRICT_BYTES
+        gbs = nops * bpo / (ms * 1e-3) / 1e9
+        res[name] = {"ms_per_call": round(ms, 4), "points": int(nops),
+                     "bytes_per_point": bpo, "achieved_gbs": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    plan.destroy()
+    del u, old
+    torch.cuda.empty_cache()
+    res["hierarchy"] = (f"3 levels of {n[0]}x{n[1]}x{n[2]} + {g.ghost} "
+                        f"ghosts, spacings h, h/2, h/4, nested centred")
+    return res
+
+
 def cpu_baseline(name, target_s=15.0):
     """The oracle on the host cores over a bounded sample of the workload:
     a z-slab of the same grid (same data, static ghosts taken from the full
@@ -656,6 +735,8 @@ def main():
         if g.npoints <= 256 ** 3:  # initial conversion of the same data
             out["adm_to_bssn"] = time_from_adm(B, torch, g, wl[4], wl[5],
                                                order)
+        if g.npoints <= 160 ** 3:  # refinement glue on this grid
+            out["amr_glue"] = time_amr_glue(B, torch, g)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
