@@ -37,13 +37,33 @@ __device__ __forceinline__ double w_mid(int m) {
   return (m == 0 || m == 3) ? -1.0 / 16.0 : 9.0 / 16.0;
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (linear id mod 8).  Give each
+// XCD a contiguous eighth of the (slot, chunk of 256 ops) space instead, so
+// that neighbouring ops -- which read overlapping coarse blocks -- share an
+// L2.  nwg is the launch's workgroup count, a multiple of 8.
+struct Work {
+  int64_t t;  // op index
+  int s;      // slot
+  bool live;
+};
+__device__ __forceinline__ Work xcd_work(int64_t nops, int64_t nchunks) {
+  const int64_t nwg = gridDim.x, b = blockIdx.x;
+  const int64_t id = (b % 8) * (nwg / 8) + b / 8;
+  Work w;
+  w.s = int(id / nchunks);
+  w.t = (id % nchunks) * 256 + threadIdx.x;
+  w.live = id < nchunks * NSLOT && w.t < nops;
+  return w;
+}
+
 __global__ void __launch_bounds__(256)
     k_amr_fill(const AmrOp* __restrict__ ops, const int64_t nops,
-               const AmrGeo* __restrict__ geo, double* const* __restrict__ u,
-               const AmrTime T) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= nops) return;
-  const int s = blockIdx.y;
+               const int64_t nchunks, const AmrGeo* __restrict__ geo,
+               double* const* __restrict__ u, const AmrTime T) {
+  const Work w = xcd_work(nops, nchunks);
+  if (!w.live) return;
+  const int64_t t = w.t;
+  const int s = w.s;
   const AmrOp op = ops[t];
   const AmrGeo gd = geo[op.dpatch], gs = geo[op.spatch];
   double* d = u[op.dpatch] + int64_t(s) * gd.sf + op.dst;
@@ -71,12 +91,13 @@ __global__ void __launch_bounds__(256)
 
 __global__ void __launch_bounds__(256)
     k_amr_restrict(const AmrOp* __restrict__ ops, const int64_t nops,
-                   const AmrGeo* __restrict__ geo,
+                   const int64_t nchunks, const AmrGeo* __restrict__ geo,
                    double* const* __restrict__ coarse,
                    const double* const* __restrict__ fine) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= nops) return;
-  const int s = blockIdx.y;
+  const Work w = xcd_work(nops, nchunks);
+  if (!w.live) return;
+  const int64_t t = w.t;
+  const int s = w.s;
   const AmrOp op = ops[t];
   const AmrGeo gd = geo[op.dpatch], gs = geo[op.spatch];
   const double* c = fine[op.spatch] + int64_t(s) * gs.sf + op.src;
@@ -96,10 +117,11 @@ hipError_t launch_amr_fill(const AmrOp* ops, int64_t nops, const AmrGeo* geo,
                            double* const* u, const AmrTime& T,
                            hipStream_t st) {
   if (nops <= 0) return hipSuccess;
-  const int64_t blocks = (nops + 255) / 256;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_amr_fill, dim3(unsigned(blocks), NSLOT), dim3(256), 0,
-                     st, ops, nops, geo, u, T);
+  const int64_t nchunks = (nops + 255) / 256;
+  const int64_t nwg = (nchunks * NSLOT + 7) / 8 * 8;
+  if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_amr_fill, dim3(unsigned(nwg)), dim3(256), 0, st, ops,
+                     nops, nchunks, geo, u, T);
   return hipGetLastError();
 }
 
@@ -107,10 +129,11 @@ hipError_t launch_amr_restrict(const AmrOp* ops, int64_t nops,
                                const AmrGeo* geo, double* const* coarse,
                                const double* const* fine, hipStream_t st) {
   if (nops <= 0) return hipSuccess;
-  const int64_t blocks = (nops + 255) / 256;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_amr_restrict, dim3(unsigned(blocks), NSLOT), dim3(256),
-                     0, st, ops, nops, geo, coarse, fine);
+  const int64_t nchunks = (nops + 255) / 256;
+  const int64_t nwg = (nchunks * NSLOT + 7) / 8 * 8;
+  if (nwg > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_amr_restrict, dim3(unsigned(nwg)), dim3(256), 0, st,
+                     ops, nops, nchunks, geo, coarse, fine);
   return hipGetLastError();
 }
 
