@@ -13,8 +13,10 @@
 // G_c has its lower child at fine index 2(G_c - D).
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "../../include/bssn.h"
@@ -23,9 +25,11 @@
 
 struct bssn_amr_plan {
   int npatch = 0, nlevel = 0, device = 0;
-  std::vector<int64_t> fill_begin, fill_count, ncopy;   // per level
+  std::vector<int64_t> fill_begin, fill_count;          // copy ops, per level
+  std::vector<int64_t> tile_begin, tile_count, nprolong; // per level
   std::vector<int64_t> restr_begin, restr_count;        // per fine level
   bssn::AmrOp* d_ops = nullptr;
+  bssn::AmrTile* d_tiles = nullptr;
   bssn::AmrGeo* d_geo = nullptr;
 };
 
@@ -55,6 +59,14 @@ struct Lat {          // one patch on its level's lattice
 int64_t storage(const Lat& p, const int64_t idx[3]) {
   return idx[0] * p.st[0] + idx[1] * p.st[1] + idx[2] * p.st[2];
 }
+
+// Prolonged points of one 8 x 8 x 8 box of a fine patch that read one
+// coarse patch: membership and the range of their block bases.
+struct TileAcc {
+  uint64_t mask[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t bmin[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
+  int64_t bmax[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
+};
 
 }  // namespace
 }  // namespace bssn
@@ -127,19 +139,24 @@ int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
   }
 
   std::vector<AmrOp> ops;
+  std::vector<AmrTile> tiles;
   bssn_amr_plan plan;
   plan.npatch = npatch;
   plan.nlevel = nlevel;
   plan.fill_begin.assign(nlevel, 0);
   plan.fill_count.assign(nlevel, 0);
-  plan.ncopy.assign(nlevel, 0);
+  plan.tile_begin.assign(nlevel, 0);
+  plan.tile_count.assign(nlevel, 0);
+  plan.nprolong.assign(nlevel, 0);
   plan.restr_begin.assign(nlevel, 0);
   plan.restr_count.assign(nlevel, 0);
   for (int L = 0; L < nlevel; ++L) {
     plan.fill_begin[L] = int64_t(ops.size());
+    plan.tile_begin[L] = int64_t(tiles.size());
     for (int p = 0; p < npatch; ++p) {
       const Lat& P = lat[p];
       if (P.level != L) continue;
+      std::map<std::array<int64_t, 4>, TileAcc> acc;  // (box z, y, x, c)
       int64_t idx[3];
       for (idx[2] = 0; idx[2] < P.n[2] + 2 * P.g; ++idx[2])
         for (idx[1] = 0; idx[1] < P.n[1] + 2 * P.g; ++idx[1])
@@ -169,25 +186,32 @@ int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
               op.spatch = q;
               op.code = 0;
               found = true;
-              ++plan.ncopy[L];
             }
-            if (!found && L == 0) continue;  // physical boundary
+            if (found) {
+              ops.push_back(op);
+              continue;
+            }
+            if (L == 0) continue;  // physical boundary
             for (int c = 0; c < npatch && !found; ++c) {
               const Lat& C = lat[c];
               if (C.level != L - 1) continue;
               int64_t b[3];
-              int code = AMR_PROLONG;
               bool in = true;
               for (int a = 0; a < 3; ++a) {
                 const int64_t q = 2 * D[3 * L + a] + G[a];
                 b[a] = floordiv(q - 1, 2) - 1 - C.off[a] + C.g;
                 in = in && b[a] >= 0 && b[a] + 3 <= C.n[a] + 2 * C.g - 1;
-                if (q % 2 == 0) code |= 2 << a;
               }
               if (!in) continue;
-              op.src = storage(C, b);
-              op.spatch = c;
-              op.code = code;
+              TileAcc& T = acc[{idx[2] / 8, idx[1] / 8, idx[0] / 8, c}];
+              const int pt = int(idx[0] % 8 + 8 * (idx[1] % 8) +
+                                 64 * (idx[2] % 8));
+              T.mask[pt >> 6] |= uint64_t(1) << (pt & 63);
+              for (int a = 0; a < 3; ++a) {
+                T.bmin[a] = b[a] < T.bmin[a] ? b[a] : T.bmin[a];
+                T.bmax[a] = b[a] > T.bmax[a] ? b[a] : T.bmax[a];
+              }
+              ++plan.nprolong[L];
               found = true;
             }
             if (!found)
@@ -197,10 +221,33 @@ int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
                           "patch holds its interpolation block",
                           p, L, (long long)idx[0], (long long)idx[1],
                           (long long)idx[2]);
-            ops.push_back(op);
           }
+      for (const auto& kv : acc) {
+        const int c = int(kv.first[3]);
+        const Lat& C = lat[c];
+        const TileAcc& A = kv.second;
+        AmrTile t{};
+        t.dpatch = p;
+        t.spatch = c;
+        int64_t o[3] = {kv.first[2] * 8, kv.first[1] * 8, kv.first[0] * 8};
+        for (int a = 0; a < 3; ++a) {
+          const int64_t N = P.n[a] + 2 * P.g;
+          t.n[a] = uint8_t(N - o[a] < 8 ? N - o[a] : 8);
+          t.c[a] = uint8_t(A.bmax[a] - A.bmin[a] + 4);
+          const int64_t q0 = 2 * D[3 * L + a] + P.off[a] + o[a] - P.g;
+          const int64_t f0 = floordiv(q0 - 1, 2);
+          const int64_t e0 = q0 - 1 - 2 * f0;
+          t.r0[a] = int32_t(f0 - 1 - C.off[a] + C.g - A.bmin[a]);
+          t.code |= int32_t(e0) << a;
+        }
+        for (int w = 0; w < 8; ++w) t.mask[w] = A.mask[w];
+        t.dst0 = storage(P, o);
+        t.src0 = storage(C, A.bmin);
+        tiles.push_back(t);
+      }
     }
     plan.fill_count[L] = int64_t(ops.size()) - plan.fill_begin[L];
+    plan.tile_count[L] = int64_t(tiles.size()) - plan.tile_begin[L];
   }
   for (int L = 1; L < nlevel; ++L) {
     plan.restr_begin[L] = int64_t(ops.size());
@@ -255,6 +302,11 @@ int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
   if (e == hipSuccess && !ops.empty())
     e = hipMemcpy(P->d_ops, ops.data(), sizeof(AmrOp) * ops.size(),
                   hipMemcpyHostToDevice);
+  if (e == hipSuccess && !tiles.empty())
+    e = hipMalloc((void**)&P->d_tiles, sizeof(AmrTile) * tiles.size());
+  if (e == hipSuccess && !tiles.empty())
+    e = hipMemcpy(P->d_tiles, tiles.data(), sizeof(AmrTile) * tiles.size(),
+                  hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     bssn_amr_plan_destroy(P);
     return hip_fail(e, "bssn_amr_plan_create upload");
@@ -269,8 +321,8 @@ int bssn_amr_plan_counts(const bssn_amr_plan* plan, int level,
   if (level < 0 || level >= plan->nlevel)
     return fail(BSSN_EINVAL, "level %d outside 0..%d", level,
                 plan->nlevel - 1);
-  counts[0] = plan->fill_count[level];
-  counts[1] = plan->ncopy[level];
+  counts[0] = plan->fill_count[level] + plan->nprolong[level];
+  counts[1] = plan->fill_count[level];
   counts[2] = plan->restr_count[level];
   return BSSN_OK;
 }
@@ -301,7 +353,7 @@ int bssn_amr_fill_ghosts(const bssn_amr_plan* plan, int level,
     if (rc) return rc;
     hipError_t e = launch_amr_fill(plan->d_ops + plan->fill_begin[0],
                                    plan->fill_count[0], plan->d_geo, u_tab,
-                                   T, (hipStream_t)stream);
+                                   (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "bssn_amr_fill_ghosts launch");
     return BSSN_OK;
   }
@@ -331,7 +383,11 @@ int bssn_amr_fill_ghosts(const bssn_amr_plan* plan, int level,
   }
   hipError_t e = launch_amr_fill(plan->d_ops + plan->fill_begin[level],
                                  plan->fill_count[level], plan->d_geo, u_tab,
-                                 T, (hipStream_t)stream);
+                                 (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = launch_amr_prolong(plan->d_tiles + plan->tile_begin[level],
+                           plan->tile_count[level], plan->d_geo, u_tab, T,
+                           (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "bssn_amr_fill_ghosts launch");
   return BSSN_OK;
 }
@@ -354,6 +410,7 @@ int bssn_amr_restrict(const bssn_amr_plan* plan, int level,
 int bssn_amr_plan_destroy(bssn_amr_plan* plan) {
   if (!plan) return BSSN_OK;
   if (plan->d_ops) (void)hipFree(plan->d_ops);
+  if (plan->d_tiles) (void)hipFree(plan->d_tiles);
   if (plan->d_geo) (void)hipFree(plan->d_geo);
   delete plan;
   return BSSN_OK;

@@ -143,10 +143,9 @@ struct TrackArgs {
 hipError_t launch_track(const TrackArgs& A, double* pos, int np, double dt,
                         hipStream_t st);
 
-// Mesh-refinement glue (bssn_amr_*): ops built on the host, one per filled
+// Mesh-refinement glue (bssn_amr_*): ops built on the host, one per copied
 // ghost point or restricted coarse point.  dst and src are element offsets
 // from the slot-0 origin of the destination and source patch states.
-enum { AMR_PROLONG = 1 };  // code bit 0; bits 1..3: x, y, z phase (1.75)
 struct AmrOp {
   int64_t dst, src;
   int32_t dpatch, spatch;
@@ -160,8 +159,23 @@ struct AmrTime {
   double w[3];                  // Lagrange weights in time
   int ntl;
 };
+// Prolonged ghost points grouped by 8 x 8 x 8 box of the fine storage grid
+// and coarse source patch: the coarse region the box's points read (at
+// most 8 per axis) is staged in LDS once per (tile, slot, time level).
+struct AmrTile {
+  int64_t dst0, src0;  // box origin in dpatch; region origin in spatch
+  int32_t dpatch, spatch;
+  int32_t r0[3];       // block base of box point 0, relative to the region
+  int32_t code;        // bit a: (q - 1) mod 2 of box point 0 along axis a
+  uint8_t n[3], c[3];  // box extents (1..8), region extents (4..8)
+  uint8_t pad[2];
+  uint64_t mask[8];    // point i + 8 j + 64 k of the box is filled
+};
 hipError_t launch_amr_fill(const AmrOp* ops, int64_t nops, const AmrGeo* geo,
-                           double* const* u, const AmrTime& T, hipStream_t st);
+                           double* const* u, hipStream_t st);
+hipError_t launch_amr_prolong(const AmrTile* tiles, int64_t ntiles,
+                              const AmrGeo* geo, double* const* u,
+                              const AmrTime& T, hipStream_t st);
 hipError_t launch_amr_restrict(const AmrOp* ops, int64_t nops,
                                const AmrGeo* geo, double* const* coarse,
                                const double* const* fine, hipStream_t st);
