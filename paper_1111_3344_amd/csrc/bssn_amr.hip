@@ -94,54 +94,90 @@ __global__ void __launch_bounds__(256)
   coarse[op.dpatch][int64_t(s) * gd.sf + op.dst] = acc;
 }
 
-// One workgroup per (tile, slot): stage the tile's coarse region for every
-// time level in LDS (coalesced rows), then each masked fine point of the
-// box interpolates from LDS with the same weights and order as k_amr_fill.
+// One workgroup per (tile, slot): stage the tile's coarse region in LDS
+// with the time levels combined (Lagrange weights in time, the same for
+// every point), then each masked fine point of the box interpolates from
+// LDS, the tensor-product weights applied one axis at a time (x, y, z).
 __global__ void __launch_bounds__(256)
     k_amr_prolong(const AmrTile* __restrict__ tiles, const int64_t ntiles,
                   const AmrGeo* __restrict__ geo,
                   double* const* __restrict__ u, const AmrTime T) {
-  __shared__ double reg[3 * 512];
+  // the region, the coarse time levels already combined (the time weights
+  // are the same for every point); pitches 9 and 81 spread a wave's reads
+  // over the LDS banks
+  __shared__ double reg[8 * 81];
   const int64_t nwg = gridDim.x, b = blockIdx.x;
   const int64_t id = (b % 8) * (nwg / 8) + b / 8;
   if (id >= ntiles * NSLOT) return;  // uniform over the workgroup
   const int s = int(id / ntiles);
-  const AmrTile tl = tiles[id % ntiles];
-  const AmrGeo gs = geo[tl.spatch], gd = geo[tl.dpatch];
-  const int cx = tl.c[0], cy = tl.c[1], cz = tl.c[2];
+  // fields read from the tile in memory: a local copy of the struct, indexed
+  // at run time (mask words), would live in scratch
+  const AmrTile* tp = tiles + id % ntiles;
+  const int dpatch = tp->dpatch, spatch = tp->spatch;
+  const AmrGeo gs = geo[spatch], gd = geo[dpatch];
+  const int cx = tp->c[0], cy = tp->c[1], cz = tp->c[2];
   const int nreg = cx * cy * cz;
-  for (int l = 0; l < T.ntl; ++l) {
-    const double* src = T.tab[l][tl.spatch] + int64_t(s) * gs.sf + tl.src0;
-    for (int e = threadIdx.x; e < nreg; e += 256) {
-      const int x = e % cx, r = e / cx, y = r % cy, z = r / cy;
-      reg[l * 512 + z * 64 + y * 8 + x] = src[z * gs.sz + y * gs.sy + x];
-    }
+  const int64_t src0 = tp->src0 + int64_t(s) * gs.sf;
+  // every load of the region issued before the first LDS store (a region
+  // holds at most 512 values: two per thread per time level), so their
+  // latencies overlap
+  double v[3][2];
+  int lds_at[2];
+  bool have[2];
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int e = threadIdx.x + it * 256;
+    have[it] = e < nreg;
+    const int x = e % cx, r = e / cx, y = r % cy, z = r / cy;
+    lds_at[it] = z * 81 + y * 9 + x;
+    const int64_t off = int64_t(z) * gs.sz + int64_t(y) * gs.sy + x;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+      if (have[it] && l < T.ntl) v[l][it] = T.tab[l][spatch][src0 + off];
   }
-  __syncthreads();
-  double* dst = u[tl.dpatch] + int64_t(s) * gd.sf + tl.dst0;
-  const int ex = tl.code & 1, ey = (tl.code >> 1) & 1, ez = (tl.code >> 2) & 1;
-  for (int pt = threadIdx.x; pt < 512; pt += 256) {
-    if (!((tl.mask[pt >> 6] >> (pt & 63)) & 1)) continue;
-    const int i = pt & 7, j = (pt >> 3) & 7, k = pt >> 6;
-    const int bx = tl.r0[0] + (ex + i) / 2, by = tl.r0[1] + (ey + j) / 2,
-              bz = tl.r0[2] + (ez + k) / 2;
-    const int px = (ex + i) & 1, py = (ey + j) & 1, pz = (ez + k) & 1;
-    const int base = bz * 64 + by * 8 + bx;
-    double val = 0.0;
-    for (int l = 0; l < T.ntl; ++l) {
-      const double* c = reg + l * 512 + base;
-      double acc = 0.0;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-          for (int ii = 0; ii < 4; ++ii)
-            acc += w_quarter(pz, kk) * w_quarter(py, jj) * w_quarter(px, ii) *
-                   c[kk * 64 + jj * 8 + ii];
-      val += T.w[l] * acc;
+  for (int it = 0; it < 2; ++it)
+    if (have[it]) {
+      double t = T.w[0] * v[0][it];
+      if (T.ntl > 1) t += T.w[1] * v[1][it];
+      if (T.ntl > 2) t += T.w[2] * v[2][it];
+      reg[lds_at[it]] = t;
     }
-    dst[k * gd.sz + j * gd.sy + i] = val;
+  __syncthreads();
+  double* dst = u[dpatch] + int64_t(s) * gd.sf + tp->dst0;
+  const int code = tp->code;
+  const int ex = code & 1, ey = (code >> 1) & 1, ez = (code >> 2) & 1;
+  const int r0x = tp->r0[0], r0y = tp->r0[1], r0z = tp->r0[2];
+  for (int pt = threadIdx.x; pt < 512; pt += 256) {
+    if (!((tp->mask[pt >> 6] >> (pt & 63)) & 1)) continue;
+    const int i = pt & 7, j = (pt >> 3) & 7, k = pt >> 6;
+    const int bx = r0x + (ex + i) / 2, by = r0y + (ey + j) / 2,
+              bz = r0z + (ez + k) / 2;
+    const int px = (ex + i) & 1, py = (ey + j) & 1, pz = (ez + k) & 1;
+    const double* c = reg + bz * 81 + by * 9 + bx;
+    double wx[4], wy[4], wz[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      wx[m] = w_quarter(px, m);
+      wy[m] = w_quarter(py, m);
+      wz[m] = w_quarter(pz, m);
+    }
+    // separable: x, then y, then z
+    double zsum = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      double ysum = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        double xsum = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+          xsum += wx[ii] * c[kk * 81 + jj * 9 + ii];
+        ysum += wy[jj] * xsum;
+      }
+      zsum += wz[kk] * ysum;
+    }
+    dst[k * gd.sz + j * gd.sy + i] = zsum;
   }
 }
 
