@@ -188,7 +188,7 @@ def time_from_adm(B, torch, g, masses, centres, order, reps=5):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
-AMR_FILL_BYTES = 232      # op (32 B) + 25 values written; coarse reads below
+AMR_FILL_BYTES = 232      # 32 B bookkeeping + 25 values written; reads below
 AMR_RESTRICT_BYTES = 1832  # op (32 B) + 25 values written + 8 children read
 
 
@@ -613,6 +613,9 @@ def main():
     ap.add_argument("--accuracy", action="store_true",
                     help="FP64 vs mixed runs of the workload for its step "
                          "count: field errors and constraint norms")
+    ap.add_argument("--amr-glue-only", action="store_true",
+                    help="only the refinement-glue timing on the workload's "
+                         "grid (JSON line)")
     ap.add_argument("--summarize-profile", nargs="+", metavar="DIR",
                     help="print a text summary of rocprofv3 CSV output "
                          "directories and exit")
@@ -638,6 +641,14 @@ def main():
         return
     if args.accuracy:
         print(json.dumps(accuracy(B, torch, args.workload)), flush=True)
+        return
+    if args.amr_glue_only:
+        from paper_1111_3344_amd import inputs as I
+        wl = WORKLOADS[args.workload]
+        gg = I.cell_centred(wl[0], wl[1], wl[2], wl[3])
+        print(json.dumps({"workload": args.workload,
+                          "amr_glue": time_amr_glue(B, torch, gg)}),
+              flush=True)
         return
     g, u, order, dt, desc = build_state(args.workload)
     N = g.npoints

@@ -333,10 +333,10 @@ typedef struct {
  * point).  Restriction: every interior point of a level-(L-1) patch whose
  * eight children lie in the interior of a level-L patch (the first in list
  * order) takes the tricubic midpoint interpolation of that patch's storage,
- * weights (-1, 9, 9, -1)/16 per axis.  Allocates the op lists on the
- * current device (one op of 32 B per filled ghost point and per restricted
- * point; level-0 ghost points inside another level-0 interior are planned
- * as copies).  *out receives the plan.  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED,
+ * weights (-1, 9, 9, -1)/16 per axis.  Allocates the plan's lists on
+ * the current device (32 B per copied ghost point and per restricted
+ * point, 112 B per 8 x 8 x 8 box of prolonged ghost points; level-0 ghost
+ * points inside another level-0 interior are planned as copies).  *out receives the plan.  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED,
  * BSSN_EHIP. */
 int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
                          bssn_amr_plan** out);
