@@ -267,6 +267,45 @@ def time_amr_glue(B, torch, g, reps=10):
     return res
 
 
+def time_multipole(B, torch, g, reps=10):
+    """bssn_multipole of a complex field (the real and imaginary parts two
+    slots of a state on the workload's grid) on the sphere r = 0.75 of the
+    half-width around the grid centre, spin -2, l <= 8, 64 x 128 points."""
+    import ctypes
+    u = torch.randn(g.total, dtype=torch.float64, device="cuda")
+    centre = [g.origin[a] + (g.n[a] - 1) * g.h[a] / 2 for a in range(3)]
+    radius = 0.75 * (g.n[0] - 1) * g.h[0] / 2
+    nt, nph, lmax = 64, 128, 8
+    work = torch.empty(2 * nt * (nph + 1), dtype=torch.float64, device="cuda")
+    coeffs = torch.empty(2 * (lmax + 1) ** 2, dtype=torch.float64,
+                         device="cuda")
+    c = (ctypes.c_double * 3)(*centre)
+    rp = ctypes.c_void_p(B.ptr(g, u).value + 8 * 17 * g.sf)
+    ip = ctypes.c_void_p(B.ptr(g, u).value + 8 * 7 * g.sf)
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    L = B.lib()
+
+    def call():
+        B._check(L.bssn_multipole(ctypes.byref(B.c_grid(g)), rp, ip, c,
+                                  radius, -2, lmax, nt, nph,
+                                  ctypes.c_void_p(work.data_ptr()),
+                                  ctypes.c_void_p(coeffs.data_ptr()), sp))
+    call()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del u, work, coeffs
+    return {"kernels": "k_gl_nodes, k_sphere_interp, k_multipole",
+            "ms_per_call": round(ms, 4), "sphere_points": nt * nph,
+            "lmax": lmax, "spin": -2, "radius": radius}
+
+
 def cpu_baseline(name, target_s=15.0):
     """The oracle on the host cores over a bounded sample of the workload:
     a z-slab of the same grid (same data, static ghosts taken from the full
@@ -748,6 +787,7 @@ def main():
                                                order)
         if g.npoints <= 160 ** 3:  # refinement glue on this grid
             out["amr_glue"] = time_amr_glue(B, torch, g)
+        out["multipole"] = time_multipole(B, torch, g)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -207,6 +207,30 @@ int bssn_from_adm(const bssn_grid* grid, const bssn_params* params,
 int bssn_track_punctures(const bssn_grid* grid, const double* u, int npunct,
                          double* pos, double dt, void* stream);
 
+/* Multipole coefficients (section "Analysis": the multipole module) of a
+ * complex grid function u = re + i im on the coordinate sphere of radius
+ * `radius` around `centre`:
+ *   C^{lm} = integral of conj(sY_lm) u r^2 dOmega,  s = spin,
+ * sY_lm Goldberg's spin-weighted harmonics (Condon-Shortley phase at
+ * s = 0), the integral over ntheta Gauss-Legendre nodes in cos(theta) times
+ * nphi uniform points in phi (exact for products of harmonics of one spin
+ * up to the node counts), u at each point by tricubic Lagrange
+ * interpolation on the 4 x 4 x 4 storage points around it (the block
+ * shifted inward at the edge of the storage grid).
+ *   re, im  device, one slot each in the grid's layout (element 0 of the
+ *           storage grid); im may be NULL (a real field)
+ *   centre  host, 3 values; radius > 0
+ *   spin    -8..8;  lmax 0..16;  ntheta 1..1024;  nphi 1..4096
+ *   work    device scratch of at least 2 ntheta (nphi + 1) doubles
+ *   coeffs  device, 2 (lmax + 1)^2 doubles: (re, im) of C^{lm} at index
+ *           l*l + l + m; zero for l < |spin|
+ * Three launches on `stream`; the sums run in a fixed order (the result is
+ * deterministic).  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED, BSSN_EHIP. */
+int bssn_multipole(const bssn_grid* grid, const double* re, const double* im,
+                   const double* centre, double radius, int spin, int lmax,
+                   int ntheta, int nphi, double* work, double* coeffs,
+                   void* stream);
+
 /* Radiative (Sommerfeld-type) outer boundary (section "Spacetime Curvature
  * Evolution", boundary conditions): the right-hand side on the ghost layers
  * of a static grid, which then become evolved boundary points.  Every

@@ -119,6 +119,10 @@ def lib():
                                            ctypes.c_double, vp]
         L.bssn_amr_restrict.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         L.bssn_amr_plan_destroy.argtypes = [vp]
+        L.bssn_multipole.argtypes = [g, vp, vp, P(ctypes.c_double),
+                                     ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     vp, vp, vp]
         L.bssn_radiative_rhs.argtypes = [g, P(ctypes.c_double),
                                          P(ctypes.c_double), ctypes.c_int,
                                          vp, vp, vp]
@@ -252,6 +256,34 @@ def bssn_track_punctures(grid, u, pos, dt, stream=None):
     _check(lib().bssn_track_punctures(
         ctypes.byref(c_grid(grid)), ptr(grid, u), pos.numel() // 3,
         ctypes.c_void_p(pos.data_ptr()), float(dt), _stream(stream)))
+
+
+def bssn_multipole(grid, re, im, centre, radius, spin, lmax, ntheta, nphi,
+                   re_slot=0, im_slot=0, stream=None):
+    """C^{lm} (complex numpy array indexed l*l + l + m) of the field whose
+    real part is slot re_slot of flat tensor re (im likewise; im may be
+    None) on the sphere of the given radius around centre."""
+    import numpy as np
+    import torch
+    for t in (re, im):
+        if t is not None and (t.dtype.itemsize != 8 or not t.is_cuda):
+            raise TypeError("fields are float64 device tensors")
+    work = torch.empty(2 * ntheta * (nphi + 1), dtype=torch.float64,
+                       device=re.device)
+    coeffs = torch.empty(2 * (lmax + 1) ** 2, dtype=torch.float64,
+                         device=re.device)
+    c = (ctypes.c_double * 3)(*[float(x) for x in centre])
+    rp = ctypes.c_void_p(ptr(grid, re).value + 8 * re_slot * grid.sf)
+    ip = (None if im is None else
+          ctypes.c_void_p(ptr(grid, im).value + 8 * im_slot * grid.sf))
+    _check(lib().bssn_multipole(ctypes.byref(c_grid(grid)), rp, ip, c,
+                                float(radius), int(spin), int(lmax),
+                                int(ntheta), int(nphi),
+                                ctypes.c_void_p(work.data_ptr()),
+                                ctypes.c_void_p(coeffs.data_ptr()),
+                                _stream(stream)))
+    out = coeffs.cpu().numpy()
+    return out[0::2] + 1j * out[1::2]
 
 
 # Values at infinity and wave speeds of the radiative boundary, per slot:

@@ -259,6 +259,48 @@ int bssn_track_punctures(const bssn_grid* grid, const double* u, int npunct,
   return BSSN_OK;
 }
 
+int bssn_multipole(const bssn_grid* grid, const double* re, const double* im,
+                   const double* centre, double radius, int spin, int lmax,
+                   int ntheta, int nphi, double* work, double* coeffs,
+                   void* stream) {
+  int rc = check_grid(grid, 4);
+  if (rc) return rc;
+  if (!re || !work || !coeffs || !centre)
+    return fail(BSSN_EINVAL, "re, centre, work and coeffs must be non-NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(centre[a]))
+      return fail(BSSN_EINVAL, "centre[%d] is not finite", a);
+  if (!(radius > 0.0) || !std::isfinite(radius))
+    return fail(BSSN_EINVAL, "radius must be finite and > 0");
+  if (spin < -8 || spin > 8) return fail(BSSN_EINVAL, "spin %d outside -8..8", spin);
+  if (lmax < 0 || lmax > 16) return fail(BSSN_EINVAL, "lmax %d outside 0..16", lmax);
+  if (ntheta < 1 || ntheta > 1024)
+    return fail(BSSN_EINVAL, "ntheta %d outside 1..1024", ntheta);
+  if (nphi < 1 || nphi > 4096)
+    return fail(BSSN_EINVAL, "nphi %d outside 1..4096", nphi);
+  MultipoleArgs A{};
+  A.re = re;
+  A.im = im;
+  for (int a = 0; a < 3; ++a) {
+    A.n[a] = grid->n[a];
+    A.origin[a] = grid->origin[a];
+    A.h[a] = grid->h[a];
+    A.centre[a] = centre[a];
+  }
+  A.ghost = grid->ghost;
+  A.sy = grid->sy;
+  A.sz = grid->sz;
+  A.radius = radius;
+  A.spin = spin;
+  A.lmax = lmax;
+  A.ntheta = ntheta;
+  A.nphi = nphi;
+  hipError_t e = launch_multipole(A, work, coeffs, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "bssn_multipole launch");
+  g_err = "no error";
+  return BSSN_OK;
+}
+
 int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
                        const double* v0, int power, const double* u,
                        double* rhs, void* stream) {

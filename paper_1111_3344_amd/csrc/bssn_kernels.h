@@ -143,6 +143,21 @@ struct TrackArgs {
 hipError_t launch_track(const TrackArgs& A, double* pos, int np, double dt,
                         hipStream_t st);
 
+// Multipole coefficients on a coordinate sphere (bssn_multipole).
+struct MultipoleArgs {
+  const double* re;  // field slots, element 0 of the storage grid
+  const double* im;  // may be null
+  int32_t n[3];
+  int32_t ghost;
+  int64_t sy, sz;
+  double origin[3], h[3];
+  double centre[3];
+  double radius;
+  int32_t spin, lmax, ntheta, nphi;
+};
+hipError_t launch_multipole(const MultipoleArgs& A, double* work,
+                            double* coeffs, hipStream_t st);
+
 // Mesh-refinement glue (bssn_amr_*): ops built on the host, one per copied
 // ghost point or restricted coarse point.  dst and src are element offsets
 // from the slot-0 origin of the destination and source patch states.

@@ -217,6 +217,30 @@ def test_amr_plan_validation():
     assert L.bssn_amr_plan_destroy(None) == B.BSSN_OK
 
 
+def test_multipole_validation():
+    L = B.lib()
+    g = I.cell_centred(8, -1, 1, 3)
+    c = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    bad_c = (ctypes.c_double * 3)(0.0, float("nan"), 0.0)
+
+    def call(re=1, im=None, cen=c, r=0.5, s=-2, lmax=4, nt=8, nph=16,
+             work=2, coeffs=3):
+        return L.bssn_multipole(ctypes.byref(B.c_grid(g)), P(re), P(im),
+                                cen, r, s, lmax, nt, nph, P(work), P(coeffs),
+                                None)
+
+    assert call(re=0) == B.BSSN_EINVAL
+    assert call(work=0) == B.BSSN_EINVAL
+    assert call(coeffs=0) == B.BSSN_EINVAL
+    assert call(cen=bad_c) == B.BSSN_EINVAL
+    assert call(r=0.0) == B.BSSN_EINVAL
+    assert call(r=float("inf")) == B.BSSN_EINVAL
+    assert call(s=9) == B.BSSN_EINVAL
+    assert call(lmax=17) == B.BSSN_EINVAL
+    assert call(nt=0) == B.BSSN_EINVAL
+    assert call(nph=4097) == B.BSSN_EINVAL
+
+
 def test_periodic_grid_must_cover_stencil():
     g = I.GridSpec((2, 8, 8), 3, (0.1,) * 3, (0,) * 3, I.BC_PERIODIC)
     assert _stage(B.c_grid(g), B.Params().c()) == B.BSSN_EINVAL
