@@ -188,6 +188,51 @@ def time_from_adm(B, torch, g, masses, centres, order, reps=5):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def nested_hierarchy(g, nlevel=3):
+    """Level 0 the grid g; level L + 1 a patch of the same size at half the
+    spacing whose cells split the cells n/4 .. 3n/4 - 1 of level L."""
+    from paper_1111_3344_amd import inputs as I
+    hier = [(0, g)]
+    for L in range(1, nlevel):
+        par = hier[-1][1]
+        h = tuple(x / 2 for x in par.h)
+        o = tuple(par.origin[a] + (par.n[a] // 4 - 0.25) * par.h[a]
+                  for a in range(3))
+        hier.append((L, I.GridSpec(tuple(par.n), par.ghost, h, o,
+                                   I.BC_STATIC)))
+    return hier
+
+
+def time_amr_step(B, torch, g, wl, order, steps=3):
+    """Berger-Oliger stepping (paper_1111_3344_amd.amr) of the workload's
+    punctures on three nested levels of its grid (nested_hierarchy): one
+    level-0 step = 1 + 2 + 4 level steps, a ghost fill per RK4 stage and
+    per level step, two restrictions.  One warm-up step, then `steps`
+    steps between device synchronisations (host clock)."""
+    from paper_1111_3344_amd import amr
+    from paper_1111_3344_amd import inputs as I
+    hier = nested_hierarchy(g)
+    u0 = [B.to_device(I.brill_lindquist(gr, wl[4], wl[5])) for _, gr in hier]
+    drv = amr.BergerOliger(hier, B.Params(fd_order=order), wl[7], u0)
+    drv.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        drv.step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    level_steps = sum(2 ** L for L, _ in hier)
+    upd = sum(gr.npoints * 2 ** L for L, gr in hier)
+    ok = all(bool(torch.isfinite(x).all()) for x in drv.u)
+    del drv, u0
+    torch.cuda.empty_cache()
+    return {"ms_per_level0_step": round(ms, 3),
+            "level_steps_per_level0_step": level_steps,
+            "fills_per_level0_step": 5 * (level_steps - 1),
+            "updates_per_s": upd / (ms * 1e-3), "finite": ok,
+            "hierarchy": "3 nested levels of the workload grid, h, h/2, h/4"}
+
+
 AMR_FILL_BYTES = 232      # 32 B bookkeeping + 25 values written; reads below
 AMR_RESTRICT_BYTES = 1832  # op (32 B) + 25 values written + 8 children read
 
@@ -201,18 +246,8 @@ def time_amr_glue(B, torch, g, reps=10):
     device data).  Timed between HIP events on the launch stream; the
     pointer tables are built before the timed region."""
     import ctypes
-    from paper_1111_3344_amd import inputs as I
-
-    def child(par):  # fine cells split coarse cells n/4 .. 3n/4 - 1
-        h = tuple(x / 2 for x in par.h)
-        o = tuple(par.origin[a] + (par.n[a] // 4 - 0.25) * par.h[a]
-                  for a in range(3))
-        return I.GridSpec(tuple(par.n), par.ghost, h, o, I.BC_STATIC)
-
     n = g.n
-    lv1 = child(g)
-    lv2 = child(lv1)
-    hier = [(0, g), (1, lv1), (2, lv2)]
+    hier = nested_hierarchy(g)
     plan = B.AmrPlan(hier)
 
     def state(gr):
@@ -788,6 +823,8 @@ def main():
         if g.npoints <= 160 ** 3:  # refinement glue on this grid
             out["amr_glue"] = time_amr_glue(B, torch, g)
         out["multipole"] = time_multipole(B, torch, g)
+        if g.npoints <= 160 ** 3:
+            out["amr_berger_oliger"] = time_amr_step(B, torch, g, wl, order)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -10,7 +10,6 @@ slots); the pointer handed to the library is the ghost corner of slot 0.
 """
 from __future__ import annotations
 
-import collections
 import ctypes
 import dataclasses
 import math
@@ -385,17 +384,22 @@ class AmrPlan:
                                           ctypes.byref(h)))
         self.h = h
         self._torch = torch
-        # tables of recent calls: a launch may still be queued when the
-        # next call builds its own
-        self._keep = collections.deque(maxlen=64)
+        # device pointer tables, one per distinct tuple of pointers: a
+        # stepping driver rotates a few buffers, so the tables are built
+        # once (a table is never freed while the plan lives, so a launch
+        # still queued keeps a valid one)
+        self._tables = {}
 
     def _table(self, states):
-        vals = []
-        for (lv, g), t in zip(self.hier, states):
-            vals.append(0 if t is None else ptr(g, t).value)
-        tab = self._torch.tensor(vals, dtype=self._torch.int64,
-                                 device="cuda")
-        self._keep.append(tab)
+        vals = tuple(0 if t is None else ptr(g, t).value
+                     for (lv, g), t in zip(self.hier, states))
+        tab = self._tables.get(vals)
+        if tab is None:
+            if len(self._tables) >= 4096:
+                raise RuntimeError("more than 4096 distinct state sets")
+            tab = self._torch.tensor(list(vals), dtype=self._torch.int64,
+                                     device="cuda")
+            self._tables[vals] = tab
         return ctypes.c_void_p(tab.data_ptr())
 
     def counts(self, level):
