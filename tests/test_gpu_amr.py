@@ -8,6 +8,8 @@ prolonged ghost points and restricted coarse points to 1e-13 relative per
 slot (normwise over the points compared: both sides sum the same 64 or 192
 products, in a different contraction); nothing else may change.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -50,6 +52,11 @@ CASES = {
     "two-level-one-time": (H.two_level, [0.0], 0.0),
     "two-level-three-times": (H.two_level, [0.0, 0.5, 1.0], 0.75),
     "three-level-two-times": (H.three_level, [0.0, 1.0], 0.5),
+    # the ghost width of 8th-order grids: wider shells, more tiles
+    "two-level-ghost5-two-times": (functools.partial(H.two_level, ghost=5),
+                                   [0.0, 1.0], 0.3),
+    "three-level-ghost5-three-times": (
+        functools.partial(H.three_level, ghost=5), [0.0, 0.5, 1.0], 0.8),
 }
 
 
@@ -133,7 +140,9 @@ def test_copy_points_bitwise(B):
     plan.destroy()
 
 
-@pytest.mark.parametrize("hfn", [H.two_level, H.three_level])
+@pytest.mark.parametrize("hfn", [H.two_level, H.three_level,
+                                 functools.partial(H.two_level, ghost=5)],
+                         ids=["two_level", "three_level", "two_level_ghost5"])
 def test_restrict_matches_oracle(B, hfn):
     hr = hfn()
     plan = B.AmrPlan(hr)
