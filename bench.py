@@ -311,7 +311,9 @@ def time_multipole(B, torch, g, reps=10):
     centre = [g.origin[a] + (g.n[a] - 1) * g.h[a] / 2 for a in range(3)]
     radius = 0.75 * (g.n[0] - 1) * g.h[0] / 2
     nt, nph, lmax = 64, 128, 8
-    work = torch.empty(2 * nt * (nph + 1), dtype=torch.float64, device="cuda")
+    chunks = min(64, (nt * nph + 255) // 256)
+    work = torch.empty(2 * nt * (nph + 1) + 2 * (lmax + 1) ** 2 * chunks,
+                       dtype=torch.float64, device="cuda")
     coeffs = torch.empty(2 * (lmax + 1) ** 2, dtype=torch.float64,
                          device="cuda")
     c = (ctypes.c_double * 3)(*centre)
@@ -336,7 +338,8 @@ def time_multipole(B, torch, g, reps=10):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     del u, work, coeffs
-    return {"kernels": "k_gl_nodes, k_sphere_interp, k_multipole",
+    return {"kernels": "k_gl_nodes, k_sphere_interp, k_multipole, "
+                       "k_multipole_sum",
             "ms_per_call": round(ms, 4), "sphere_points": nt * nph,
             "lmax": lmax, "spin": -2, "radius": radius}
 

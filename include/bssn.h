@@ -221,10 +221,12 @@ int bssn_track_punctures(const bssn_grid* grid, const double* u, int npunct,
  *           storage grid); im may be NULL (a real field)
  *   centre  host, 3 values; radius > 0
  *   spin    -8..8;  lmax 0..16;  ntheta 1..1024;  nphi 1..4096
- *   work    device scratch of at least 2 ntheta (nphi + 1) doubles
+ *   work    device scratch of at least
+ *           2 ntheta (nphi + 1) + 2 (lmax + 1)^2 min(64, ceil(ntheta nphi
+ *           / 256)) doubles
  *   coeffs  device, 2 (lmax + 1)^2 doubles: (re, im) of C^{lm} at index
  *           l*l + l + m; zero for l < |spin|
- * Three launches on `stream`; the sums run in a fixed order (the result is
+ * Four launches on `stream`; the sums run in a fixed order (the result is
  * deterministic).  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED, BSSN_EHIP. */
 int bssn_multipole(const bssn_grid* grid, const double* re, const double* im,
                    const double* centre, double radius, int spin, int lmax,

@@ -267,8 +267,9 @@ def bssn_multipole(grid, re, im, centre, radius, spin, lmax, ntheta, nphi,
     for t in (re, im):
         if t is not None and (t.dtype.itemsize != 8 or not t.is_cuda):
             raise TypeError("fields are float64 device tensors")
-    work = torch.empty(2 * ntheta * (nphi + 1), dtype=torch.float64,
-                       device=re.device)
+    chunks = min(64, (ntheta * nphi + 255) // 256)
+    work = torch.empty(2 * ntheta * (nphi + 1) + 2 * (lmax + 1) ** 2 * chunks,
+                       dtype=torch.float64, device=re.device)
     coeffs = torch.empty(2 * (lmax + 1) ** 2, dtype=torch.float64,
                          device=re.device)
     c = (ctypes.c_double * 3)(*[float(x) for x in centre])

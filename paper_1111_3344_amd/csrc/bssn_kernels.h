@@ -155,6 +155,12 @@ struct MultipoleArgs {
   double radius;
   int32_t spin, lmax, ntheta, nphi;
 };
+// Point chunks per (l, m) (at most 64): the partial sums take
+// 2 (lmax + 1)^2 chunks doubles of the workspace after the point values.
+inline int multipole_chunks(int ntheta, int nphi) {
+  const int c = (ntheta * nphi + 255) / 256;
+  return c < 64 ? c : 64;
+}
 hipError_t launch_multipole(const MultipoleArgs& A, double* work,
                             double* coeffs, hipStream_t st);
 

@@ -3,15 +3,17 @@
 // multipole module projects a field interpolated onto spheres onto
 // spin-weighted spherical harmonics, C^lm = integral conj(sY_lm) u r^2 dOmega).
 //
-// Three launches:
+// Four launches:
 //   k_gl_nodes      Gauss-Legendre nodes and weights in cos(theta), by Newton
 //                   iteration on the Legendre recurrence (one thread per node);
 //   k_sphere_interp one thread per sphere point (theta_j, phi_k): the
 //                   tricubic interpolation of the real and imaginary parts
 //                   (4 x 4 x 4 storage points, block clamped into the grid);
-//   k_multipole     one workgroup per (l, m): the sum over the sphere of
-//                   conj(sY_lm) u w_j (2 pi / n_phi), a fixed-order tree
-//                   reduction (deterministic), times r^2.
+//   k_multipole     one workgroup per (l, m, chunk of the points): the sum
+//                   of conj(sY_lm) u w_j (2 pi / n_phi) over its points, a
+//                   fixed-order tree reduction;
+//   k_multipole_sum one thread per (l, m): the chunks added in order (the
+//                   result is deterministic), times r^2.
 // sY_lm (Goldberg's sum) is evaluated with half-angle powers,
 //   sin^{2l-k}(theta/2) cos^{k}(theta/2), k = 2r + s - m in [0, 2l],
 // so no cotangent is formed.
@@ -65,7 +67,7 @@ __global__ void __launch_bounds__(64)
     dp = n * (z * p1 - p0) / (z * z - 1.0);
     const double dz = p1 / dp;
     z -= dz;
-    if (fabs(dz) < 1e-16) break;
+    if (fabs(dz) <= 1e-15 * fabs(z)) break;  // dz = 0 at the middle node
   }
   // the weight from the derivative at the converged node
   double p0 = 1.0, p1 = z;
@@ -132,9 +134,9 @@ __global__ void __launch_bounds__(64)
 __global__ void __launch_bounds__(256)
     k_multipole(const MultipoleArgs A, const double* __restrict__ x,
                 const double* __restrict__ w, const double* __restrict__ val,
-                double* __restrict__ coeffs) {
+                const int nchunk, double* __restrict__ part) {
   __shared__ double sre[256], sim[256];
-  const int q = blockIdx.x;
+  const int q = blockIdx.x / nchunk, chunk = blockIdx.x % nchunk;
   int l = 0;
   while ((l + 1) * (l + 1) <= q) ++l;
   const int m = q - l * l - l;
@@ -147,7 +149,7 @@ __global__ void __launch_bounds__(256)
              (4.0 * M_PI * fact(l + s) * fact(l - s)));
     const double dphi = 2.0 * M_PI / A.nphi;
     const int npts = A.ntheta * A.nphi;
-    for (int p = threadIdx.x; p < npts; p += 256) {
+    for (int p = chunk * 256 + threadIdx.x; p < npts; p += nchunk * 256) {
       const int j = p / A.nphi, k = p % A.nphi;
       const double ct = x[j];
       const double sh = sqrt(fmax(0.0, 0.5 * (1.0 - ct)));
@@ -182,10 +184,25 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double r2 = A.radius * A.radius;
-    coeffs[2 * q] = sre[0] * r2;
-    coeffs[2 * q + 1] = sim[0] * r2;
+    part[2 * (q * nchunk + chunk)] = sre[0];
+    part[2 * (q * nchunk + chunk) + 1] = sim[0];
   }
+}
+
+// One thread per (l, m): the chunks' partial sums added in chunk order.
+__global__ void __launch_bounds__(64)
+    k_multipole_sum(const int nq, const int nchunk, const double radius,
+                    const double* __restrict__ part,
+                    double* __restrict__ coeffs) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    re += part[2 * (q * nchunk + c)];
+    im += part[2 * (q * nchunk + c) + 1];
+  }
+  coeffs[2 * q] = re * radius * radius;
+  coeffs[2 * q + 1] = im * radius * radius;
 }
 
 }  // namespace
@@ -204,8 +221,15 @@ hipError_t launch_multipole(const MultipoleArgs& A, double* work,
                      A, x, val);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_multipole, dim3((A.lmax + 1) * (A.lmax + 1)),
-                     dim3(256), 0, st, A, x, w, val, coeffs);
+  const int nq = (A.lmax + 1) * (A.lmax + 1);
+  const int nchunk = multipole_chunks(A.ntheta, A.nphi);
+  double* part = val + 2 * int64_t(npts);
+  hipLaunchKernelGGL(k_multipole, dim3(nq * nchunk), dim3(256), 0, st, A, x,
+                     w, val, nchunk, part);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_multipole_sum, dim3((nq + 63) / 64), dim3(64), 0, st,
+                     nq, nchunk, A.radius, part, coeffs);
   return hipGetLastError();
 }
 
