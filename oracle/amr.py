@@ -113,6 +113,42 @@ def _prolong_block(cgrid, x):
     return base, wts
 
 
+def ghost_value(hier, level, states, coarse_states, tw, p, i, j, k):
+    """The value (all slots) of ghost point (i, j, k) of patch p on level
+    `level`: a sibling's copy, or the prolongation with time weights tw;
+    None for a level-0 ghost that no sibling covers."""
+    grid = hier[p][1]
+    x = [_coord(grid, (i, j, k)[a], a) for a in range(3)]
+    for q, (lq, gq) in enumerate(hier):
+        if q == p or lq != level:
+            continue
+        idx = _index_of(gq, x, interior=True)
+        if idx is not None:
+            src = _view(gq, states[q])
+            return src[:, idx[2], idx[1], idx[0]].copy()
+    if level == 0:
+        return None
+    for q, (lq, gq) in enumerate(hier):
+        if lq != level - 1:
+            continue
+        blk = _prolong_block(gq, x)
+        if blk is None:
+            continue
+        (bx, by, bz), (wx, wy, wz) = blk
+        val = np.zeros(NSLOT)
+        for tl, w_t in enumerate(tw):
+            c = _view(gq, coarse_states[tl][q])
+            acc = np.zeros(NSLOT)
+            for kk in range(4):
+                for jj in range(4):
+                    for ii in range(4):
+                        acc += (wz[kk] * wy[jj] * wx[ii] *
+                                c[:, bz + kk, by + jj, bx + ii])
+            val += w_t * acc
+        return val
+    raise ValueError(f"ghost point {x} of patch {p} not covered")
+
+
 def fill_ghosts(hier, level, states, coarse_states, t_src, t):
     """Fill the ghost points of every level-`level` patch in place.
 
@@ -129,49 +165,44 @@ def fill_ghosts(hier, level, states, coarse_states, t_src, t):
             continue
         dst = _view(grid, states[p])
         for (i, j, k) in _ghost_points(grid):
-            x = [_coord(grid, (i, j, k)[a], a) for a in range(3)]
-            done = False
-            for q, (lq, gq) in enumerate(hier):
-                if q == p or lq != level:
-                    continue
-                idx = _index_of(gq, x, interior=True)
-                if idx is not None:
-                    src = _view(gq, states[q])
-                    dst[:, k, j, i] = src[:, idx[2], idx[1], idx[0]]
-                    done = True
-                    break
-            if done or level == 0:
-                continue
-            for q, (lq, gq) in enumerate(hier):
-                if lq != level - 1:
-                    continue
-                blk = _prolong_block(gq, x)
-                if blk is None:
-                    continue
-                (bx, by, bz), (wx, wy, wz) = blk
-                val = np.zeros(NSLOT)
-                for tl, w_t in enumerate(tw):
-                    c = _view(gq, coarse_states[tl][q])
-                    acc = np.zeros(NSLOT)
-                    for kk in range(4):
-                        for jj in range(4):
-                            for ii in range(4):
-                                acc += (wz[kk] * wy[jj] * wx[ii] *
-                                        c[:, bz + kk, by + jj, bx + ii])
-                    val += w_t * acc
+            val = ghost_value(hier, level, states, coarse_states, tw, p, i,
+                              j, k)
+            if val is not None:
                 dst[:, k, j, i] = val
-                done = True
-                break
-            if not done:
-                raise ValueError(f"ghost point {x} of patch {p} not covered")
     return states
+
+
+def restricted_value(hier, level, fine_states, c, i, j, k):
+    """The restricted value (all slots) of interior point (i, j, k) of the
+    level - 1 patch c, or None if no level-`level` interior holds its
+    eight children."""
+    w = lagrange(1.5, [0, 1, 2, 3])   # (-1, 9, 9, -1) / 16
+    cg = hier[c][1]
+    x = [_coord(cg, (i, j, k)[a], a) for a in range(3)]
+    for f, (lf, fg) in enumerate(hier):
+        if lf != level:
+            continue
+        lo = [x[a] - fg.h[a] / 2 for a in range(3)]
+        hi = [x[a] + fg.h[a] / 2 for a in range(3)]
+        ilo = _index_of(fg, lo, interior=True)
+        if ilo is None or _index_of(fg, hi, True) is None:
+            continue
+        src = _view(fg, fine_states[f])
+        b = [ilo[a] - 1 for a in range(3)]
+        acc = np.zeros(NSLOT)
+        for kk in range(4):
+            for jj in range(4):
+                for ii in range(4):
+                    acc += (w[kk] * w[jj] * w[ii] *
+                            src[:, b[2] + kk, b[1] + jj, b[0] + ii])
+        return acc
+    return None
 
 
 def restrict(hier, level, fine_states, coarse_states):
     """Put the level-`level` solution back into the level - 1 patches (in
     place on coarse_states) where a coarse point's children lie in a fine
     interior."""
-    w = lagrange(1.5, [0, 1, 2, 3])   # (-1, 9, 9, -1) / 16
     for c, (lc, cg) in enumerate(hier):
         if lc != level - 1:
             continue
@@ -180,24 +211,8 @@ def restrict(hier, level, fine_states, coarse_states):
         for k in range(g, g + cg.n[2]):
             for j in range(g, g + cg.n[1]):
                 for i in range(g, g + cg.n[0]):
-                    x = [_coord(cg, (i, j, k)[a], a) for a in range(3)]
-                    for f, (lf, fg) in enumerate(hier):
-                        if lf != level:
-                            continue
-                        lo = [x[a] - fg.h[a] / 2 for a in range(3)]
-                        hi = [x[a] + fg.h[a] / 2 for a in range(3)]
-                        ilo = _index_of(fg, lo, interior=True)
-                        if ilo is None or _index_of(fg, hi, True) is None:
-                            continue
-                        src = _view(fg, fine_states[f])
-                        b = [ilo[a] - 1 for a in range(3)]
-                        acc = np.zeros(NSLOT)
-                        for kk in range(4):
-                            for jj in range(4):
-                                for ii in range(4):
-                                    acc += (w[kk] * w[jj] * w[ii] *
-                                            src[:, b[2] + kk, b[1] + jj,
-                                                b[0] + ii])
-                        dst[:, k, j, i] = acc
-                        break
+                    val = restricted_value(hier, level, fine_states, c, i, j,
+                                           k)
+                    if val is not None:
+                        dst[:, k, j, i] = val
     return coarse_states

@@ -56,3 +56,14 @@ def bo_level(h=0.2, ghost=3):
     f0 = child(c0, (5, 5, 5), (6, 6, 6), ghost)
     f1 = sibling(f0, (6, 0, 0))
     return [(0, c0), (0, c1), (1, f0), (1, f1)]
+
+
+def nested(g, nlevel=3):
+    """Level 0 the grid g; level L + 1 a patch of the same size at half the
+    spacing whose cells split the cells n/4 .. 3n/4 - 1 of level L."""
+    hier = [(0, g)]
+    for L in range(1, nlevel):
+        par = hier[-1][1]
+        hier.append((L, child(par, tuple(x // 4 for x in par.n), par.n,
+                              par.ghost)))
+    return hier

@@ -70,3 +70,24 @@ def test_polynomial_field_textbook_coefficient(B):
     want = np.zeros(16, complex)
     want[2] = r ** 3 * math.sqrt(4 * math.pi / 3)
     assert np.allclose(got, want, rtol=0, atol=1e-12), got
+
+
+def test_maximum_sizes_closed_form(B):
+    """ntheta = 1024, nphi = 4096, l <= 16: the field z - c_z still projects
+    onto C^{10} = r^3 sqrt(4 pi / 3) alone.  Goldberg's alternating sum
+    loses digits at high l (about 1e-12 absolute at l = 16 against scipy's
+    harmonics), hence 1e-9 of C^{10} for the other coefficients."""
+    g = I.GridSpec((16, 15, 17), 3, (0.25,) * 3, (-2.0, -1.9, -2.1),
+                   I.BC_STATIC)
+    c, r = (0.1, -0.05, 0.02), 1.3
+    u = g.empty()
+    X, Y, Z = g.mesh()
+    g.view(u)[0] = Z - c[2]
+    print("[multipole] maximum sizes", flush=True)
+    got = B.bssn_multipole(g, B.to_device(u), None, c, r, 0, 16, 1024, 4096)
+    c10 = r ** 3 * math.sqrt(4 * math.pi / 3)
+    assert abs(got[2] - c10) <= 1e-12 * c10
+    rest = np.delete(got, 2)
+    print(f"[multipole] maximum sizes: max |other C| / C10 = "
+          f"{np.abs(rest).max() / c10:.2e}", flush=True)
+    assert np.abs(rest).max() <= 1e-9 * c10
