@@ -1,4 +1,8 @@
-"""Compile the oracle's C source into oracle/liboracle.so with gcc."""
+"""Compile the oracle's C source into oracle/liboracle.so with gcc.
+
+Test infrastructure only: the library build compiles the checker beside
+the product; only the tests, the smoke check and the benchmark's CPU
+baseline load it."""
 import os
 import subprocess
 
