@@ -203,7 +203,7 @@ def nested_hierarchy(g, nlevel=3):
     return hier
 
 
-def time_amr_step(B, torch, g, wl, order, steps=3):
+def time_amr_step(B, torch, g, wl, order, steps=3, precision=None):
     """Berger-Oliger stepping (paper_1111_3344_amd.amr) of the workload's
     punctures on three nested levels of its grid (nested_hierarchy): one
     level-0 step = 1 + 2 + 4 level steps, a ghost fill per RK4 stage and
@@ -213,7 +213,9 @@ def time_amr_step(B, torch, g, wl, order, steps=3):
     from paper_1111_3344_amd import inputs as I
     hier = nested_hierarchy(g)
     u0 = [B.to_device(I.brill_lindquist(gr, wl[4], wl[5])) for _, gr in hier]
-    drv = amr.BergerOliger(hier, B.Params(fd_order=order), wl[7], u0)
+    prm = B.Params(fd_order=order,
+                   precision=B.BSSN_FP64 if precision is None else precision)
+    drv = amr.BergerOliger(hier, prm, wl[7], u0)
     drv.step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -828,6 +830,8 @@ def main():
         out["multipole"] = time_multipole(B, torch, g)
         if g.npoints <= 160 ** 3:
             out["amr_berger_oliger"] = time_amr_step(B, torch, g, wl, order)
+            out["amr_berger_oliger_mixed"] = time_amr_step(
+                B, torch, g, wl, order, precision=B.BSSN_MIXED)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
