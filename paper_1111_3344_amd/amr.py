@@ -9,7 +9,7 @@ This module only orders calls: every value is computed by the library
 bssn_amr_restrict for the coarse points under a fine patch).  Python keeps
 the times and rotates the time-level buffers.
 
-Per level L (spacing h_0 / 2^L, step dt_0 / 2^L) the driver keeps three
+Per level L (spacing h_0 / 2^L, step dt_0 / 2^L) the stepper keeps three
 time levels of every patch: the current state and the two before it.  The
 ghost points of each RK4 stage input of level L >= 1 are filled at the
 stage's time (t, t + dt/2, t + dt/2, t + dt) from the time levels of level
@@ -25,7 +25,7 @@ STAGE_C = (0.0, 0.5, 0.5, 1.0)
 
 class BergerOliger:
     """hier: list of (level, grid); u0: device states (one per patch) at
-    t = 0, taken over by the driver; dt0: the level-0 step."""
+    t = 0, taken over by the stepper; dt0: the level-0 step."""
 
     def __init__(self, hier, params, dt0, u0):
         import torch
