@@ -309,3 +309,32 @@ def test_constraints_nonfinite_counted(B):
     _, _, _, n0 = O.constraints(g, O.params(), u)
     assert n[7] == n0[7] >= 1 and n[6] == n0[6]
     assert np.isfinite(n[:6]).all()
+
+
+@pytest.mark.parametrize("nan", [False, True])
+def test_constraint_norms_closed_form(B, nan):
+    """The GPU's norms on the closed-form state of the oracle's norm pins
+    (flat metric, K linear in x, constant Gt^x; two centres whose excised
+    sets are counted by hand, one NaN reaching 10 points): N_used and
+    N_nonfinite exactly, the RMS and maxima to 1e-13."""
+    import test_oracle_norms as T
+    g = T._grid()
+    u = T._state(g)
+    used = np.ones((T.N,) * 3, bool)
+    for cx in (3, 4):
+        for d in [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0),
+                  (0, 0, 1), (0, 0, -1)]:
+            used[3 + d[2], 3 + d[1], cx + d[0]] = False
+    bad = 0
+    if nan:
+        g.interior(u)[I.TRK, 1, 1, 5] = np.nan
+        for x, y, z in [(5, 1, 1), (4, 1, 1), (6, 1, 1), (3, 1, 1), (5, 0, 1),
+                        (5, 2, 1), (5, 3, 1), (5, 1, 0), (5, 1, 2), (5, 1, 3)]:
+            used[z, y, x] = False
+        bad = 10
+    du = B.to_device(u)
+    norms = torch.zeros(8, dtype=torch.float64, device="cuda")
+    B.bssn_constraints(g, B.Params(), du, norms,
+                       centres=[(0.0, 0.0, 0.0), (0.5, 0.0, 0.0)], r_exc=0.5)
+    torch.cuda.synchronize()
+    T._check(norms.cpu().numpy(), T._closed_form_norms(used), nonfinite=bad)
