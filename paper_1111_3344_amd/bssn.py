@@ -128,7 +128,7 @@ def lib():
         if hasattr(L, "batch_patches_plan"):
             L.batch_patches_plan.argtypes = [
                 ctypes.c_int, P(bssn_grid), p, P(vp), P(vp), P(vp), P(vp),
-                ctypes.c_double, ctypes.c_int, P(vp), vp]
+                P(ctypes.c_double), ctypes.c_int, P(vp), vp]
             L.batch_patches.argtypes = [vp, ctypes.c_int, vp]
             L.batch_patches_unbatched.argtypes = [vp, ctypes.c_int, vp]
             L.batch_patches_describe.argtypes = [vp, ctypes.c_int,
@@ -168,15 +168,26 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def ptr(grid, t):
+def ptr(grid, t, nslot=25):
     """Device address of the ghost corner of slot 0 of flat tensor t (or of
-    a raw device address t that holds such a flat buffer)."""
+    a raw device address t that holds such a flat buffer).  A tensor must be
+    a contiguous float64 device tensor holding at least off0 + nslot * sf
+    elements (nslot: the slots the call reads or writes), since the kernels
+    address every slot from this one pointer."""
     if t is None:
         return None
     if isinstance(t, int):
         return ctypes.c_void_p(t + 8 * grid.off0)
-    if t.dtype.itemsize != 8:
+    if t.dtype.itemsize != 8 or not t.dtype.is_floating_point:
         raise TypeError("state buffers are float64")
+    if not t.is_cuda:
+        raise TypeError("state buffers are device tensors")
+    if not t.is_contiguous():
+        raise TypeError("state buffers are contiguous")
+    need = grid.off0 + nslot * grid.sf
+    if t.numel() < need:
+        raise ValueError(f"buffer of {t.numel()} elements is shorter than "
+                         f"the {need} that {nslot} slots of this grid need")
     return ctypes.c_void_p(t.data_ptr() + 8 * grid.off0)
 
 
@@ -226,7 +237,8 @@ def bssn_constraints(grid, params, u, norms, H=None, M=None, G=None,
     arr = (ctypes.c_double * max(1, len(flat)))(*flat)
     _check(lib().bssn_constraints(
         ctypes.byref(c_grid(grid)), ctypes.byref(_params(params)),
-        ptr(grid, u), ptr(grid, H), ptr(grid, M), ptr(grid, G), arr,
+        ptr(grid, u), ptr(grid, H, 1), ptr(grid, M, 3), ptr(grid, G, 3),
+        arr,
         len(flat) // 3, float(r_exc), ctypes.c_void_p(norms.data_ptr()),
         _stream(stream)))
 
@@ -243,7 +255,7 @@ def bssn_from_adm(grid, params, adm, u, stream=None):
     """BSSN state u (flat state-shaped tensor) from the ADM variables adm
     (flat tensor of off0 + 16 sf elements: g_ij, K_ij, alpha, beta^i)."""
     _check(lib().bssn_from_adm(ctypes.byref(c_grid(grid)),
-                               ctypes.byref(_params(params)), ptr(grid, adm),
+                               ctypes.byref(_params(params)), ptr(grid, adm, 16),
                                ptr(grid, u), _stream(stream)))
 
 
@@ -273,9 +285,11 @@ def bssn_multipole(grid, re, im, centre, radius, spin, lmax, ntheta, nphi,
     coeffs = torch.empty(2 * (lmax + 1) ** 2, dtype=torch.float64,
                          device=re.device)
     c = (ctypes.c_double * 3)(*[float(x) for x in centre])
-    rp = ctypes.c_void_p(ptr(grid, re).value + 8 * re_slot * grid.sf)
+    rp = ctypes.c_void_p(ptr(grid, re, re_slot + 1).value +
+                         8 * re_slot * grid.sf)
     ip = (None if im is None else
-          ctypes.c_void_p(ptr(grid, im).value + 8 * im_slot * grid.sf))
+          ctypes.c_void_p(ptr(grid, im, im_slot + 1).value +
+                          8 * im_slot * grid.sf))
     _check(lib().bssn_multipole(ctypes.byref(c_grid(grid)), rp, ip, c,
                                 float(radius), int(spin), int(lmax),
                                 int(ntheta), int(nphi),
@@ -330,10 +344,16 @@ def batch_patches_plan(grids, params, u, a, b, acc, dt, autotune=True,
     for bufs in (u, a, b, acc):
         arrs.append((ctypes.c_void_p * n)(*[ptr(g, t) for g, t in
                                              zip(grids, bufs)]))
+    # dt: one value for every patch, or one per patch
+    dts = ([float(dt)] * n if isinstance(dt, (int, float)) else
+           [float(x) for x in dt])
+    if len(dts) != n:
+        raise ValueError(f"{len(dts)} time steps for {n} patches")
+    dta = (ctypes.c_double * n)(*dts)
     h = ctypes.c_void_p()
     _check(lib().batch_patches_plan(n, G, ctypes.byref(_params(params)),
                                     arrs[0], arrs[1], arrs[2], arrs[3],
-                                    float(dt), int(autotune),
+                                    dta, int(autotune),
                                     ctypes.byref(h), _stream(stream)))
     return BatchPlan(h, (u, a, b, acc))
 

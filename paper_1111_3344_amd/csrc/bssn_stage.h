@@ -141,6 +141,9 @@ __device__ __forceinline__ bool tile_needs_fp64(const Patch& P, bool active,
   __syncthreads();
   double m = wmin[0];
   for (int w = 1; w < nw; ++w) m = fmin(m, wmin[w]);
+  // every wave has read wmin before any wave can overwrite it for the
+  // next plane of a multi-plane workgroup
+  __syncthreads();
   return m < thr;
 }
 
