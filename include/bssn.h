@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define BSSN_ABI_VERSION 1
+#define BSSN_ABI_VERSION 2
 
 enum {
   BSSN_OK = 0,
@@ -275,12 +275,16 @@ int bssn_mixed_tile_count(const bssn_grid* grid, const bssn_params* params,
 typedef struct bssn_batch_plan bssn_batch_plan;
 
 /* Build a plan for npatch independent static-boundary patches sharing one
- * bssn_params and one dt.  Per patch p (host arrays of device pointers):
+ * bssn_params.  Per patch p (host arrays; the buffers are device pointers):
  *   grids[p]  host, the patch's grid (bc must be BSSN_BC_STATIC)
  *   u[p]      device state buffer holding u_n; receives u_{n+1} after each
  *             step
  *   a[p], b[p]  device scratch state buffers with the same ghosts as u[p]
  *   acc[p]    device scratch state buffer (ghosts unused)
+ *   dt[p]     host, the patch's RK4 time step (finite, >= 0); patches of a
+ *             refinement hierarchy step with their own level's dt
+ * Every buffer must be device memory whose allocation holds the grid's 25
+ * slots from the pointer on (checked with the allocation's address range).
  * autotune = 1 times every kernel tile (shape and z-block depth, see
  * batch_patches_describe) the layout allows, per patch size class, on the
  * given buffers, and keeps the fastest (tuning runs stage 0 only, which
@@ -303,7 +307,7 @@ typedef struct bssn_batch_plan bssn_batch_plan;
 int batch_patches_plan(int npatch, const bssn_grid* grids,
                        const bssn_params* params, double* const* u,
                        double* const* a, double* const* b,
-                       double* const* acc, double dt, int autotune,
+                       double* const* acc, const double* dt, int autotune,
                        bssn_batch_plan** plan, void* stream);
 
 /* Advance every patch of the plan by nsteps RK4 steps (one graph launch per

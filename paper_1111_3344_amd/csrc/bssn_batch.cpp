@@ -560,7 +560,7 @@ extern "C" {
 int batch_patches_plan(int npatch, const bssn_grid* grids,
                        const bssn_params* params, double* const* u,
                        double* const* a, double* const* b,
-                       double* const* acc, double dt, int autotune,
+                       double* const* acc, const double* dt, int autotune,
                        bssn_batch_plan** plan, void* stream) {
   if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
   *plan = nullptr;
@@ -568,9 +568,13 @@ int batch_patches_plan(int npatch, const bssn_grid* grids,
   if (rc) return rc;
   if (npatch < 1 || npatch > kMaxPatches)
     return fail(BSSN_EINVAL, "npatch = %d outside 1..%d", npatch, kMaxPatches);
-  if (!grids || !u || !a || !b || !acc)
-    return fail(BSSN_EINVAL, "grids and the buffer arrays must be non-NULL");
-  if (!std::isfinite(dt)) return fail(BSSN_EINVAL, "dt is not finite");
+  if (!grids || !u || !a || !b || !acc || !dt)
+    return fail(BSSN_EINVAL, "grids, dt and the buffer arrays must be "
+                "non-NULL");
+  for (int p = 0; p < npatch; ++p)
+    if (!std::isfinite(dt[p]) || dt[p] < 0.0)
+      return fail(BSSN_EINVAL, "patch %d: dt = %g is not a finite value "
+                  ">= 0", p, dt[p]);
   {
     const int flags = autotune & ~0xff, v = autotune & 0xff;
     const bool ok =
@@ -611,7 +615,7 @@ int batch_patches_plan(int npatch, const bssn_grid* grids,
   for (int s = 0; s < 4; ++s) P->hp[s].resize(npatch);
   for (int p = 0; p < npatch; ++p) {
     Patch base = make_patch(&grids[p]);
-    base.dt = dt;
+    base.dt = dt[p];
     base.u_n = u[p];
     base.acc = acc[p];
     const double* us[4] = {u[p], a[p], b[p], a[p]};
@@ -631,6 +635,15 @@ int batch_patches_plan(int npatch, const bssn_grid* grids,
         delete P;
         return fail(BSSN_EINVAL, "patch %d: a buffer is not device memory "
                     "of this device", p);
+      }
+      // every slot of the state must lie inside the buffer's allocation
+      const uint64_t need = uint64_t(base.sf) * NSLOT * 8u;
+      const uint64_t beg = reinterpret_cast<uint64_t>(ptr);
+      const uint64_t lo = reinterpret_cast<uint64_t>(r.base);
+      if (beg < lo || beg - lo + need > uint64_t(r.size)) {
+        delete P;
+        return fail(BSSN_EINVAL, "patch %d: a buffer's allocation ends "
+                    "before the %d slots of its grid", p, NSLOT);
       }
       P->ptrs.push_back(ptr);
       P->ranges.push_back(r);

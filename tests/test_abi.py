@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
     L = B.lib()
     for n in _declared():
         assert hasattr(L, n), f"{n} declared in bssn.h but not exported"
-    assert B.bssn_abi_version() == 1
+    assert B.bssn_abi_version() == 2
 
 
 def _grid(**kw):
@@ -252,8 +252,10 @@ def _plan(grids, prm, bufs=None, dt=0.1, autotune=0, out=True):
     if bufs is None:
         bufs = [[8 * (4 * p + i + 1) for p in range(n)] for i in range(4)]
     arrs = [(ctypes.c_void_p * max(1, n))(*b) for b in bufs]
+    dts = dt if isinstance(dt, (list, tuple)) else [dt] * max(1, n)
+    dta = None if dt is None else (ctypes.c_double * len(dts))(*dts)
     h = ctypes.c_void_p()
-    return B.lib().batch_patches_plan(n, G, ctypes.byref(prm), *arrs, dt,
+    return B.lib().batch_patches_plan(n, G, ctypes.byref(prm), *arrs, dta,
                                       autotune,
                                       ctypes.byref(h) if out else None, None)
 
@@ -268,6 +270,12 @@ def test_batch_plan_validation():
     assert _plan([], prm) == B.BSSN_EINVAL
     assert _plan([g], prm, out=False) == B.BSSN_EINVAL
     assert _plan([g], prm, dt=float("inf")) == B.BSSN_EINVAL
+    # per-patch time steps: every entry finite and >= 0, the array present
+    assert _plan([g], prm, dt=None) == B.BSSN_EINVAL
+    assert _plan([g, g], prm, dt=[0.1, float("nan")]) == B.BSSN_EINVAL
+    assert "patch 1" in B.bssn_last_error()
+    assert _plan([g, g], prm, dt=[-0.05, 0.1]) == B.BSSN_EINVAL
+    assert "patch 0" in B.bssn_last_error()
     assert _plan([g], prm, autotune=2) == B.BSSN_EINVAL
     assert _plan([g], prm, autotune=B.BSSN_BATCH_TILE(5)) == B.BSSN_EINVAL
     assert _plan([g], prm, autotune=0x400) == B.BSSN_EINVAL

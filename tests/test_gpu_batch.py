@@ -108,6 +108,28 @@ def test_batched_lds_equals_rk4_stage_bitwise(B):
     plan.destroy()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_per_patch_dt_bitwise(B, precision):
+    """One plan over patches stepped with two different time steps (the
+    patches of two refinement levels): each equals rk4_step with its own
+    dt, bitwise."""
+    grids, us = host_set(6, 63 + precision, 20, 44)
+    bufs = device_set(B, us)
+    prm = B.Params(precision=precision)
+    dts = [0.03125 if p % 2 == 0 else 0.015625 for p in range(len(grids))]
+    plan = B.batch_patches_plan(grids, prm, *bufs, dts, autotune=0)
+    B.batch_patches(plan, 2)
+    got = results(grids, bufs[0])
+    for p, (g, x) in enumerate(zip(grids, us)):
+        du = B.to_device(x)
+        a, b, acc = du.clone(), du.clone(), torch.zeros_like(du)
+        for _ in range(2):
+            B.rk4_step(g, prm, dts[p], du, a, b, acc)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[p], g.interior(du.cpu().numpy())), p
+    plan.destroy()
+
+
 def test_batched_matches_oracle(B):
     grids, us = host_set(5, 77, 18, 34)
     bufs = device_set(B, us)
