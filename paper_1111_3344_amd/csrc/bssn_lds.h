@@ -95,30 +95,42 @@ struct LdsBufs {
   double* b[Geo::NBUF];
 };
 
-// Per-lane DMA byte offsets (within one slot) of the granules this lane
-// moves for a tile at (x0, y0, z0) (interior coordinates).
+// Per-lane part of the DMA byte offsets (within one slot) of the granules
+// this lane moves: the granule's place in the box, independent of the tile.
+// The tile adds a wave-uniform byte offset (dma_tile_base), so one set of
+// per-lane registers serves every tile.
 template <class Geo>
-__device__ __forceinline__ void dma_offsets(const Patch& P, int x0, int y0,
-                                            int z0, int wave, int lane,
-                                            uint32_t (&off)[Geo::L]) {
-  const int g = P.ghost;
+__device__ __forceinline__ void dma_lane_offsets(const Patch& P, int wave,
+                                                 int lane,
+                                                 uint32_t (&off)[Geo::L]) {
 #pragma unroll
   for (int j = 0; j < Geo::L; ++j) {
     const int q = (wave * Geo::L + j) * 64 + lane;
     const int col = q % (Geo::W / 2);
     const int row = q / (Geo::W / 2);
     const int yy = row % Geo::H, zz = row / Geo::H;
-    const int64_t e = int64_t(z0 + zz + g - Geo::R) * P.sz +
-                      int64_t(y0 + yy + g - Geo::R) * P.sy +
-                      (x0 + g - Geo::R - 1) + 2 * col;
-    // Padding lanes (granules past the box) fill the buffer's pad with the
-    // zeros of an offset beyond the slot (slots are < 2^31 bytes), without
-    // traffic.  The one granule that can start 8 bytes before the slot
-    // (ghost = R, grid corner) has offset 2^32 - 8: its first element (the
-    // alignment column, never read) is out of range, and its second wraps
-    // to offset 0, the slot's first element, which it is.
+    const int64_t e = int64_t(zz) * P.sz + int64_t(yy) * P.sy + 2 * col;
+    // Padding lanes (granules past the box) take an offset at or beyond
+    // 2^31, so that with any tile base below 2^31 the sum stays out of the
+    // slot (slots are < 2^31 bytes): their granules fill the buffer's pad
+    // with zeros, without traffic.
     off[j] = q < Geo::G ? uint32_t(e * 8) : 0x80000000u;
   }
+}
+
+// Byte offset of the box origin (x0 - R - 1, y0 - R, z0 - R) of the tile
+// at interior coordinates (x0, y0, z0), uniform over the workgroup.  The
+// one box that starts 8 bytes before the slot (ghost = R, grid corner) has
+// base 2^32 - 8: its first granule's first element (the alignment column,
+// never read) is out of range, and its second element wraps to offset 0,
+// the slot's first element, which it is.
+template <class Geo>
+__device__ __forceinline__ uint32_t dma_tile_base(const Patch& P, int x0,
+                                                  int y0, int z0) {
+  const int g = P.ghost;
+  const int64_t e = int64_t(z0 + g - Geo::R) * P.sz +
+                    int64_t(y0 + g - Geo::R) * P.sy + (x0 + g - Geo::R - 1);
+  return __builtin_amdgcn_readfirstlane(uint32_t(e * 8));
 }
 
 // One buffer->LDS DMA instruction: every lane moves the 16 bytes at
@@ -201,14 +213,15 @@ template <class Geo>
 __device__ __forceinline__ void dma_issue(const Patch& P, int slot,
                                           double* buf, int wave,
                                           const uint32_t (&off)[Geo::L],
-                                          uint32_t skip) {
+                                          uint32_t tbase, uint32_t skip) {
   static_assert(Geo::L <= 16, "skip mask holds 16 instructions per kind");
   const v4i r = slot_dma_rsrc(P.u_s, P.sf, slot, int32_t(P.sf * 8));
   const uint32_t l0 = lds_addr(buf) + uint32_t(wave * Geo::L) * 1024u;
   const int sh = needs_mixed(slot) ? 16 : 0;
 #pragma unroll
   for (int j = 0; j < Geo::L; ++j) {
-    const uint32_t o = off[j] | ((skip << (31 - (sh + j))) & 0x80000000u);
+    const uint32_t o =
+        (off[j] + tbase) | ((skip << (31 - (sh + j))) & 0x80000000u);
     dma16(r, o, l0 + j * 1024u);
   }
 }
@@ -281,8 +294,8 @@ struct LdLds {
   const Patch* P;
   double* ring;            // NBUF buffers of BUFD doubles
   double* sc;              // centre block
-  const uint32_t* off_cur;  // this tile's DMA offsets
-  const uint32_t* off_nxt;  // next tile's
+  const uint32_t* off;     // per-lane DMA offsets within a box
+  uint32_t tb_cur, tb_nxt;  // box base of this tile and of the next one
   int nxt[3];              // next tile's origin (centre block prefetch)
   int pbase;               // (k * NSLOT) mod NBUF
   int wave, lane, tid;
@@ -348,15 +361,13 @@ struct LdLds {
     __builtin_amdgcn_s_barrier();
     const int q = p + Geo::NBUF - 1;  // phase to prefetch
     uint32_t o[Geo::L];
-    if (q < NSLOT) {
 #pragma unroll
-      for (int j = 0; j < Geo::L; ++j) o[j] = off_cur[j];
-      dma_issue<Geo>(*P, kPhaseSlot[q], buffer(q), wave, o, skip);
-    } else {
-#pragma unroll
-      for (int j = 0; j < Geo::L; ++j) o[j] = off_nxt[j];
-      dma_issue<Geo>(*P, kPhaseSlot[q - NSLOT], buffer(q), wave, o, skip);
-    }
+    for (int j = 0; j < Geo::L; ++j) o[j] = off[j];
+    if (q < NSLOT)
+      dma_issue<Geo>(*P, kPhaseSlot[q], buffer(q), wave, o, tb_cur, skip);
+    else
+      dma_issue<Geo>(*P, kPhaseSlot[q - NSLOT], buffer(q), wave, o, tb_nxt,
+                     skip);
     if (p == kCentrePhase)
       centre_dma(*P, sc, nxt[0], nxt[1], nxt[2], wave, lane);
   }
@@ -511,14 +522,13 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
   const int tx = lane & 15, ty = lane >> 4, tz = wave;
   const int ntile_mine = Wk.count();
   if (ntile_mine <= 0) return;
-  uint32_t offA[Geo::L], offB[Geo::L];
+  uint32_t off[Geo::L];
+  dma_lane_offsets<Geo>(P, wave, lane, off);
   int x0, y0, z0, xn, yn, zn;
-  {
-    Wk.origin(0, x0, y0, z0);
-    dma_offsets<Geo>(P, x0, y0, z0, wave, lane, offA);
-    Wk.origin(ntile_mine > 1 ? 1 : 0, xn, yn, zn);
-    dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
-  }
+  Wk.origin(0, x0, y0, z0);
+  uint32_t tbA = dma_tile_base<Geo>(P, x0, y0, z0);
+  Wk.origin(ntile_mine > 1 ? 1 : 0, xn, yn, zn);
+  uint32_t tbB = dma_tile_base<Geo>(P, xn, yn, zn);
   // TRIM: DMA only the granules each slot reads (the out-of-range lanes
   // still cost their address slot, and the mask costs a register)
   const uint32_t skip = TRIM ? dma_skip_mask<Geo>(wave, lane) : 0u;
@@ -526,7 +536,8 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
   centre_dma(P, sc, x0, y0, z0, wave, lane);
 #pragma unroll
   for (int q = 0; q < Geo::NBUF - 1; ++q)
-    dma_issue<Geo>(P, kPhaseSlot[q], ring + q * Geo::BUFD, wave, offA, skip);
+    dma_issue<Geo>(P, kPhaseSlot[q], ring + q * Geo::BUFD, wave, off, tbA,
+                   skip);
 
   const int32_t nbytes = int32_t(P.sf * 8);
   const uint32_t sy8 = uint32_t(P.sy) * 8u, sz8 = uint32_t(P.sz) * 8u;
@@ -544,8 +555,9 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     ld.P = &P;
     ld.ring = ring;
     ld.sc = sc;
-    ld.off_cur = offA;
-    ld.off_nxt = offB;
+    ld.off = off;
+    ld.tb_cur = tbA;
+    ld.tb_nxt = tbB;
     ld.nxt[0] = xn;
     ld.nxt[1] = yn;
     ld.nxt[2] = zn;
@@ -591,12 +603,11 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     prev_stores = computed && __builtin_amdgcn_ballot_w64(active) != 0
                       ? epilogue_stores(stage)
                       : 0;
-    // next tile: its offsets become current, prepare the one after
-#pragma unroll
-    for (int j = 0; j < Geo::L; ++j) offA[j] = offB[j];
+    // next tile: its box base becomes current, prepare the one after
+    tbA = tbB;
     if (k + 2 < ntile_mine) {
       Wk.origin(k + 2, xn, yn, zn);
-      dma_offsets<Geo>(P, xn, yn, zn, wave, lane, offB);
+      tbB = dma_tile_base<Geo>(P, xn, yn, zn);
     }
   }
   // drain outstanding DMA (the last tile prefetched a next one that is not
