@@ -44,29 +44,64 @@ namespace bssn {
 
 template <int ORDER>
 struct TileGeo;
+// Box and ring geometry.  A box of G 16-byte granules is moved by NI DMA
+// instructions of 64 lanes, at most L per wave (waves 0..2 issue L, the last
+// wave the rest, NI - 3L); a buffer holds exactly NI * 64 granules.
+// Mixed second derivatives (SHMIX): the inner first-difference sums of the
+// tile's mixed stencils are formed once per position and shared through a
+// scratch array of MIXD doubles (MX is the reach of the centred stencils).
+// Order 4 has LDS to spare: every wave issues L instructions (the box is
+// padded to 4L), and its mixed stencils (2 x 2 inner sums per pair) are too
+// short for the shared scheme's extra barrier to pay (measured 14% slower
+// on the 256^3 grid).
 template <>
 struct TileGeo<4> {
-  static constexpr int R = 3, TX = 16, TY = 4, TZ = 4;
+  static constexpr int R = 3, MX = 2, TX = 16, TY = 4, TZ = 4;
   static constexpr int W = 24;  // (TX + 2R + 1) rounded up to even
   static constexpr int H = TY + 2 * R, D = TZ + 2 * R;
   static constexpr int G = W * H * D / 2;    // granules per box
   static constexpr int L = (G + 255) / 256;  // DMA instructions per wave
+  static constexpr int NI = 4 * L;           // DMA instructions per box
   static constexpr int NBUF = 5;             // ring of boxes in LDS; it
                                              // divides NSLOT, so every
                                              // phase's buffer is static
-  static constexpr int BUFD = L * 256 * 2;   // doubles per buffer
+  static constexpr int BUFD = NI * 64 * 2;   // doubles per buffer
   static constexpr bool EARLY_EPI = true;    // epilogue loads at kEpiSlot
+  static constexpr bool SHMIX = false;
 };
+// Order 8: the ring of three boxes and the centre block leave 8 KB of the
+// 160 KB; trimming each buffer to the NI = 43 instructions its box needs
+// (instead of 44) makes room for the mixed-derivative scratch, which
+// removes 3/4 of the mixed stencils' LDS reads and a quarter of the FP64
+// instructions.
 template <>
 struct TileGeo<8> {
-  static constexpr int R = 5, TX = 16, TY = 4, TZ = 4;
+  static constexpr int R = 5, MX = 4, TX = 16, TY = 4, TZ = 4;
   static constexpr int W = 28;
   static constexpr int H = TY + 2 * R, D = TZ + 2 * R;
   static constexpr int G = W * H * D / 2;
-  static constexpr int L = (G + 255) / 256;
+  static constexpr int NI = (G + 63) / 64;
+  static constexpr int L = (NI + 3) / 4;
   static constexpr int NBUF = 3;
-  static constexpr int BUFD = L * 256 * 2;
+  static constexpr int BUFD = NI * 64 * 2;
   static constexpr bool EARLY_EPI = false;  // no registers to hold them
+  static constexpr bool SHMIX = true;
+};
+
+// Layout of the shared mixed-derivative scratch (elements of the point
+// function's type): PX, the y-sums at the tile's positions extended by MX
+// in x ([TZ][TY][TX + 2 MX]); QX, the z-sums at the same positions; PZ, the
+// y-sums at the tile's x, y positions on the MX planes below and above the
+// tile ([2 MX][TY][TX]).  Every part is a whole number of 64-entry chunks.
+template <class Geo>
+struct MixGeo {
+  static constexpr int M = Geo::MX, XW = Geo::TX + 2 * M;
+  static constexpr int NX = Geo::TZ * Geo::TY * XW;  // entries of PX (QX)
+  static constexpr int NZ = 2 * M * Geo::TY * Geo::TX;
+  static constexpr int NE = 2 * NX + NZ;
+  static constexpr int NC = NE / 64;          // chunks
+  static constexpr int NR = (NC + 3) / 4;     // chunks per wave (at most)
+  static_assert(NX % 64 == 0 && NZ % 64 == 0, "whole chunks per part");
 };
 
 // The same box geometry with a ring of NB buffers.
@@ -79,6 +114,11 @@ struct GeoRing : Base {
 // point function fits the 256 registers that takes; the FP64 one does not).
 template <int ORDER>
 using GeoF32 = GeoRing<TileGeo<ORDER>, 3>;
+// doubles of mixed-derivative scratch a kernel with geometry Geo declares
+template <class Geo>
+constexpr int mix_doubles() {
+  return Geo::SHMIX ? MixGeo<Geo>::NE : 2;
+}
 
 static_assert(TileGeo<4>::TX == kLdsTile[0] && TileGeo<4>::TY == kLdsTile[1] &&
                   TileGeo<4>::TZ == kLdsTile[2] &&
@@ -152,6 +192,9 @@ __device__ __forceinline__ v4i dma_rsrc(const double* base, int32_t nbytes) {
   return r;
 }
 __device__ __forceinline__ void dma16(v4i r, uint32_t voff, uint32_t lds) {
+  // the LDS address is uniform; say so, so that it stays in an SGPR even
+  // where a uniform branch around the call hides that from the compiler
+  lds = __builtin_amdgcn_readfirstlane(lds);
   asm volatile(
       "s_mov_b32 m0, %2\n\t"
       "s_nop 0\n\t"
@@ -218,8 +261,11 @@ __device__ __forceinline__ void dma_issue(const Patch& P, int slot,
   const v4i r = slot_dma_rsrc(P.u_s, P.sf, slot, int32_t(P.sf * 8));
   const uint32_t l0 = lds_addr(buf) + uint32_t(wave * Geo::L) * 1024u;
   const int sh = needs_mixed(slot) ? 16 : 0;
+  // the last wave has NI - 3L instructions
+  const bool last = __builtin_amdgcn_readfirstlane(wave) == 3;
 #pragma unroll
   for (int j = 0; j < Geo::L; ++j) {
+    if (Geo::NI < 4 * Geo::L && j >= Geo::NI - 3 * Geo::L && last) continue;
     const uint32_t o =
         (off[j] + tbase) | ((skip << (31 - (sh + j))) & 0x80000000u);
     dma16(r, o, l0 + j * 1024u);
@@ -286,6 +332,37 @@ __device__ __forceinline__ void vm_wait_extra(int extra) {
 // short stretch of algebra remain.
 constexpr int kEpiSlot = BETX;
 
+// Per-lane entry positions of the shared mixed-derivative scratch: for each
+// chunk this lane's wave fills (chunk 4r + wave), the box element of the
+// entry's lowest tap (y - M for y sums, z - M for z sums).
+template <class Geo>
+__device__ __forceinline__ void mix_entries(int wave, int lane,
+                                            int (&o)[MixGeo<Geo>::NR]) {
+  using MG = MixGeo<Geo>;
+  constexpr int M = MG::M, XW = MG::XW, R = Geo::R, W = Geo::W, H = Geo::H;
+#pragma unroll
+  for (int r = 0; r < MG::NR; ++r) {
+    const int e = (4 * r + wave) * 64 + lane;
+    int x, y, z;  // box coordinates of the lowest tap
+    if (e < 2 * MG::NX) {  // PX (y sums) or QX (z sums), x-extended
+      const int i = e < MG::NX ? e : e - MG::NX;
+      const int ix = i % XW, ty = (i / XW) % Geo::TY, tz = i / (XW * Geo::TY);
+      x = ix - M + R + 1;
+      y = ty + R - (e < MG::NX ? M : 0);
+      z = tz + R - (e < MG::NX ? 0 : M);
+    } else {  // PZ: y sums on the planes beyond the tile
+      const int i = e - 2 * MG::NX;
+      const int tx = i % Geo::TX, ty = (i / Geo::TX) % Geo::TY;
+      const int pz = i / (Geo::TX * Geo::TY);
+      const int zr = pz < M ? pz - M : Geo::TZ + pz - M;
+      x = tx + R + 1;
+      y = ty + R - M;
+      z = zr + R;
+    }
+    o[r] = e < MG::NE ? (z * H + y) * W + x : 0;
+  }
+}
+
 // Loader used by point_rhs inside the pipelined kernel.  Phase p of the
 // k-th tile of a workgroup is global phase k*NSLOT + p and uses ring buffer
 // (k*NSLOT + p) mod NBUF.
@@ -318,6 +395,11 @@ struct LdLds {
   // register with immediate offsets instead of hoisting (and spilling) a
   // base address per buffer out of the tile loop
   mutable const lds_double* pc;
+  // shared mixed derivatives: the current phase's box, the scratch array
+  // and this lane's entry positions in a box (lowest tap, elements)
+  mutable const lds_double* box;
+  void* mix;
+  static constexpr bool kSharedMixed = Geo::SHMIX;
 
   __device__ __forceinline__ double* buffer(int p) const {
     return ring + ((pbase + p) % Geo::NBUF) * Geo::BUFD;
@@ -333,6 +415,7 @@ struct LdLds {
     const lds_double* b = (const lds_double*)buffer(p) + cidx;
     asm volatile("" : "+v"(b));
     pc = b;
+    if constexpr (Geo::SHMIX) box = (const lds_double*)buffer(p);
   }
   // one pipeline step at phase p (0 <= p < NSLOT)
   __device__ __forceinline__ void phase(int p) const {
@@ -354,10 +437,20 @@ struct LdLds {
     if (p <= Geo::NBUF - 2)
       extra = prev_stores +
               (p <= PE - NSLOT + Geo::NBUF - 1 ? prev_loads : 0);
-    if (p > kCentrePhase && p <= kCentrePhase + Geo::NBUF - 1)
-      vm_wait_extra<(Geo::NBUF - 2) * Geo::L + kCentreL>(extra);
-    else
-      vm_wait_extra<(Geo::NBUF - 2) * Geo::L>(extra);
+    // DMA instructions per phase: L, and NI - 3L in the last wave
+    constexpr int L3 = Geo::NI - 3 * Geo::L;
+    const bool centre = p > kCentrePhase && p <= kCentrePhase + Geo::NBUF - 1;
+    if (wave == 3 && L3 < Geo::L) {
+      if (centre)
+        vm_wait_extra<(Geo::NBUF - 2) * L3 + kCentreL>(extra);
+      else
+        vm_wait_extra<(Geo::NBUF - 2) * L3>(extra);
+    } else {
+      if (centre)
+        vm_wait_extra<(Geo::NBUF - 2) * Geo::L + kCentreL>(extra);
+      else
+        vm_wait_extra<(Geo::NBUF - 2) * Geo::L>(extra);
+    }
     __builtin_amdgcn_s_barrier();
     const int q = p + Geo::NBUF - 1;  // phase to prefetch
     uint32_t o[Geo::L];
@@ -387,7 +480,81 @@ struct LdLds {
   __device__ __forceinline__ double pl(int, int a, int i, int b, int j) const {
     return pc[kC + i * str(a) + j * str(b)];
   }
+
+  // The three mixed second derivatives of the current phase's slot at this
+  // thread's point, as tensor products of the centred first-difference
+  // stencil: d_x d_y u = sum_i a_i (Sy(x+i) - Sy(x-i)) with the inner sums
+  // Sy(x') = sum_j a_j (u(x', y+j) - u(x', y-j)), likewise d_x d_z (inner z
+  // sums at x-shifted points) and d_y d_z = d_z of the inner y sums.  Every
+  // inner sum the tile needs is formed once by one lane (MixGeo layout),
+  // written to LDS, and read back after a barrier by the lanes that need
+  // it, instead of each lane forming the 2M inner sums of each pair itself.
+  // Every wave calls it at the same phases (it holds a barrier).
+  template <int ORDER, typename T>
+  __device__ __forceinline__ void mixed3(T ihxy, T ihxz, T ihyz, T& dxy,
+                                         T& dxz, T& dyz) const {
+    using F = FD<ORDER>;
+    using MG = MixGeo<Geo>;
+    constexpr int M = MG::M, XW = MG::XW, NX = MG::NX;
+    constexpr int SY = Geo::W, SZ = Geo::W * Geo::H;
+    typedef __attribute__((address_space(3))) T lds_t;
+    lds_t* mx = (lds_t*)mix;
+    // positions derived from an opaque copy of the lane number, so that
+    // they are formed here rather than hoisted out of the tile loop (where
+    // they would hold registers through every phase)
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    int eo[MG::NR];
+    mix_entries<Geo>(wave, ln, eo);
+#pragma unroll
+    for (int r = 0; r < MG::NR; ++r) {
+      const int c = 4 * r + wave;  // chunk: uniform over the wave
+      if (4 * r + 3 >= MG::NC && c >= MG::NC) continue;
+      const lds_double* b = box + eo[r];
+      T v = T(0);
+      if (c >= NX / 64 && c < 2 * NX / 64) {  // QX: sums along z
+#pragma unroll
+        for (int j = 1; j <= M; ++j)
+          v += T(F::a(j)) * T(b[(M + j) * SZ] - b[(M - j) * SZ]);
+      } else {  // PX, PZ: sums along y
+#pragma unroll
+        for (int j = 1; j <= M; ++j)
+          v += T(F::a(j)) * T(b[(M + j) * SY] - b[(M - j) * SY]);
+      }
+      mx[c * 64 + lane] = v;
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    const int tx = ln & 15, ty = ln >> 4;
+    // lowest x tap (x - M) of this point in PX and QX
+    const lds_t* px = mx + (wave * Geo::TY + ty) * XW + tx;
+    T a = T(0), q = T(0);
+#pragma unroll
+    for (int i = 1; i <= M; ++i) {
+      a += T(F::a(i)) * (px[M + i] - px[M - i]);
+      q += T(F::a(i)) * (px[NX + M + i] - px[NX + M - i]);
+    }
+    dxy = a * ihxy;
+    dxz = q * ihxz;
+    // y sums at (x, y, z + k): PX inside the tile, PZ on the planes beyond
+    const lds_t* pxc = mx + ty * XW + tx + M;
+    const lds_t* pzc = mx + 2 * NX + ty * Geo::TX + tx;
+    T d = T(0);
+#pragma unroll
+    for (int i = 1; i <= M; ++i) {
+      const int zp = wave + i, zm = wave - i;  // uniform
+      const T vp = zp < Geo::TZ ? pxc[zp * Geo::TY * XW]
+                                : pzc[(zp - Geo::TZ + M) * Geo::TY * Geo::TX];
+      const T vm = zm >= 0 ? pxc[zm * Geo::TY * XW]
+                           : pzc[(zm + M) * Geo::TY * Geo::TX];
+      d += T(F::a(i)) * (vp - vm);
+    }
+    dyz = d * ihyz;
+    keep(dxy);
+    keep(dxz);
+    keep(dyz);
+  }
 };
+
 
 // Tile walk.  Tiles are numbered z fastest within an (x, y) column:
 // t = iz + ntz * (ix + ntx * iy).  Workgroup b owns the contiguous range of
@@ -515,7 +682,8 @@ template <int ORDER, int TP, bool TRIM, class Geo = TileGeo<ORDER>,
           class WK = Walk>
 __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
                                           const int stage, const WK& Wk,
-                                          double* ring, double* sc) {
+                                          double* ring, double* sc,
+                                          double* mixs) {
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -555,6 +723,7 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     ld.P = &P;
     ld.ring = ring;
     ld.sc = sc;
+    ld.mix = mixs;
     ld.off = off;
     ld.tb_cur = tbA;
     ld.tb_nxt = tbB;
@@ -648,10 +817,11 @@ __global__ void __launch_bounds__(256)
   using Geo = TileGeo<ORDER>;
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  __shared__ __attribute__((aligned(16))) double mixs[mix_doubles<Geo>()];
   // trimmed DMA where measured faster: not at order 4, where the mask
   // register costs a spill
   lds_tiles<ORDER, TP_F64, ORDER == 8>(P, G, stage, walk_of(M, gridDim.x),
-                                       ring, sc);
+                                       ring, sc, mixs);
 }
 
 // One patch, mixed precision, first launch: the FP32 tiles.  At order 4
@@ -665,8 +835,9 @@ __global__ void __launch_bounds__(256)
   using Geo = GeoF32<ORDER>;
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  __shared__ __attribute__((aligned(16))) double mixs[mix_doubles<Geo>()];
   lds_tiles<ORDER, TP_F32, true, Geo>(P, G, stage, walk_of(M, gridDim.x),
-                                      ring, sc);
+                                      ring, sc, mixs);
 }
 
 // Tiles named by an LDS list of tile numbers (TileMap numbering).
@@ -678,6 +849,16 @@ struct ListWalk {
   __device__ __forceinline__ void origin(int k, int& x0, int& y0,
                                          int& z0) const {
     tile_origin(t[k], ntx, ntz, x0, y0, z0);
+  }
+};
+
+// One tile (TileMap numbering), its number held in a register.
+struct OneWalk {
+  int t, ntx, ntz;
+  __device__ __forceinline__ int count() const { return 1; }
+  __device__ __forceinline__ void origin(int, int& x0, int& y0,
+                                         int& z0) const {
+    tile_origin(t, ntx, ntz, x0, y0, z0);
   }
 };
 
@@ -744,8 +925,11 @@ __global__ void __launch_bounds__(256)
   using Geo = TileGeo<ORDER>;
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  __shared__ __attribute__((aligned(16))) double mixs[mix_doubles<Geo>()];
   __shared__ int list[256];
-  __shared__ int wcnt[4];
+  // the 4 per-wave counts of compact_flags live in the mixed-derivative
+  // scratch, which is idle between lds_tiles calls (the LDS is full)
+  int* wcnt = (int*)mixs;
   const int tid = threadIdx.x;
   int lo, hi;
   walk_range(blockIdx.x, gridDim.x, M.ntiles, lo, hi);
@@ -761,7 +945,7 @@ __global__ void __launch_bounds__(256)
     const int n = compact_flags(f, t, list, wcnt);
     if (n > 0) {
       const ListWalk w{(const lds_int*)list, n, M.ntx, M.ntz};
-      lds_tiles<ORDER, TP_F64, ORDER == 8>(P, G, stage, w, ring, sc);
+      lds_tiles<ORDER, TP_F64, ORDER == 8>(P, G, stage, w, ring, sc, mixs);
     }
     __syncthreads();  // ring, sc, list and wcnt are reused
   }
@@ -778,6 +962,7 @@ __global__ void __launch_bounds__(256)
   using Geo = TileGeo<ORDER>;
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  __shared__ __attribute__((aligned(16))) double mixs[mix_doubles<Geo>()];
   const int q = walk_pos(blockIdx.x, gridDim.x);
   const int i0 = wstart[q], i1 = wstart[q + 1];
   for (int i = i0; i < i1; ++i) {
@@ -786,7 +971,7 @@ __global__ void __launch_bounds__(256)
     const Walk w = walk_contig(it.tlo, it.thi - it.tlo, it.ntx, it.ntz);
     // trimmed DMA always: many patches at once miss L2 more often, so the
     // saved traffic matters more than the register
-    lds_tiles<ORDER, TP_F64, true>(P, G, stage, w, ring, sc);
+    lds_tiles<ORDER, TP_F64, true>(P, G, stage, w, ring, sc, mixs);
     __builtin_amdgcn_s_barrier();  // every wave is done with ring and sc
   }
 }
@@ -806,6 +991,7 @@ __global__ void __launch_bounds__(256)
   using Geo = GeoF32<ORDER>;
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
+  __shared__ __attribute__((aligned(16))) double mixs[mix_doubles<Geo>()];
   const int bp = blockIdx.x;
   const bool xcd = (nwg & 7) == 0;
   const int b = xcd ? 8 * ((bp >> 3) / split) + (bp & 7) : bp / split;
@@ -818,7 +1004,7 @@ __global__ void __launch_bounds__(256)
     const int n = it.thi - it.tlo;
     const int lo = it.tlo + n * h / split, hi = it.tlo + n * (h + 1) / split;
     const Walk w = walk_contig(lo, hi - lo, it.ntx, it.ntz);
-    lds_tiles<ORDER, TP_F32, true, Geo>(P, G, stage, w, ring, sc);
+    lds_tiles<ORDER, TP_F32, true, Geo>(P, G, stage, w, ring, sc, mixs);
     __builtin_amdgcn_s_barrier();  // every wave is done with ring and sc
   }
 }
@@ -836,8 +1022,9 @@ __global__ void __launch_bounds__(256)
   using Geo = TileGeo<ORDER>;
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
-  __shared__ int list[256], ltile[256];
-  __shared__ int wcnt[4];
+  __shared__ __attribute__((aligned(16))) double mixs[mix_doubles<Geo>()];
+  __shared__ int list[256];
+  int* wcnt = (int*)mixs;  // idle between lds_tiles calls (the LDS is full)
   const int tid = threadIdx.x;
   int lo, hi;
   walk_range(blockIdx.x, gridDim.x, ncand, lo, hi);
@@ -853,14 +1040,12 @@ __global__ void __launch_bounds__(256)
       f = tile_lapse_min_global(P, x0, y0, z0) < G.alpha_thr;
     }
     const int n = compact_flags(f, c0 + tid, list, wcnt);
-    if (tid < n) ltile[tid] = cand[list[tid]].tile;  // for the walks
-    __syncthreads();
     for (int k = 0; k < n; ++k) {
-      const Patch P = patches[cand[list[k]].patch];
-      const ListWalk w{(const lds_int*)(ltile + k), 1,
-                       (P.n[0] + kLdsTile[0] - 1) / kLdsTile[0],
-                       (P.n[2] + kLdsTile[2] - 1) / kLdsTile[2]};
-      lds_tiles<ORDER, TP_F64, true>(P, G, stage, w, ring, sc);
+      const TileRef r = cand[list[k]];
+      const Patch P = patches[r.patch];
+      const OneWalk w{r.tile, (P.n[0] + kLdsTile[0] - 1) / kLdsTile[0],
+                      (P.n[2] + kLdsTile[2] - 1) / kLdsTile[2]};
+      lds_tiles<ORDER, TP_F64, true>(P, G, stage, w, ring, sc, mixs);
       __syncthreads();  // every wave is done with ring and sc
     }
     __syncthreads();  // the lists and wcnt are reused

@@ -214,6 +214,30 @@ __device__ __forceinline__ T mixed(const L& ld, int s, int a, int b, T ihab) {
   return v;
 }
 
+// Loaders that form the three mixed derivatives of a slot together (sharing
+// inner sums across the tile) declare kSharedMixed = true and mixed3().
+template <class L, class = void>
+struct SharedMixed {
+  static constexpr bool value = false;
+};
+template <class L>
+struct SharedMixed<L, decltype(void(L::kSharedMixed))> {
+  static constexpr bool value = L::kSharedMixed;
+};
+
+// d_x d_y, d_x d_z, d_y d_z of slot s at the point.
+template <int ORDER, typename T, class L>
+__device__ __forceinline__ void mixed_all(const L& ld, int s, T ihxy, T ihxz,
+                                          T ihyz, T& dxy, T& dxz, T& dyz) {
+  if constexpr (SharedMixed<L>::value) {
+    ld.template mixed3<ORDER, T>(ihxy, ihxz, ihyz, dxy, dxz, dyz);
+  } else {
+    dxy = mixed<ORDER, T>(ld, s, 0, 1, ihxy);
+    dxz = mixed<ORDER, T>(ld, s, 0, 2, ihxz);
+    dyz = mixed<ORDER, T>(ld, s, 1, 2, ihyz);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T t_exp(T x);
 template <>
@@ -291,9 +315,8 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
     r[GXX + m] =
         star<ORDER, T, true, true>(ld, GXX + m, cw, ih, ih2, dgt[m], d2);
     BSSN_PHASE();
-    const T dxy = mixed<ORDER, T>(ld, GXX + m, 0, 1, ihxy);
-    const T dxz = mixed<ORDER, T>(ld, GXX + m, 0, 2, ihxz);
-    const T dyz = mixed<ORDER, T>(ld, GXX + m, 1, 2, ihyz);
+    T dxy, dxz, dyz;
+    mixed_all<ORDER, T>(ld, GXX + m, ihxy, ihxz, ihyz, dxy, dxz, dyz);
     Rt[m] = T(-0.5) * (gu[0] * d2[0] + gu[3] * d2[1] + gu[5] * d2[2] +
                        T(2) * (gu[1] * dxy + gu[2] * dxz + gu[4] * dyz));
     keep(Rt[m]);
@@ -400,9 +423,7 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
     dd[3] = d2[1];
     dd[5] = d2[2];
     BSSN_PHASE();
-    dd[1] = mixed<ORDER, T>(ld, PHI, 0, 1, ihxy);
-    dd[2] = mixed<ORDER, T>(ld, PHI, 0, 2, ihxz);
-    dd[4] = mixed<ORDER, T>(ld, PHI, 1, 2, ihyz);
+    mixed_all<ORDER, T>(ld, PHI, ihxy, ihxz, ihyz, dd[1], dd[2], dd[4]);
     T DD[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m)
@@ -453,9 +474,7 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
     dd[3] = d2[1];
     dd[5] = d2[2];
     BSSN_PHASE();
-    dd[1] = mixed<ORDER, T>(ld, ALP, 0, 1, ihxy);
-    dd[2] = mixed<ORDER, T>(ld, ALP, 0, 2, ihxz);
-    dd[4] = mixed<ORDER, T>(ld, ALP, 1, 2, ihyz);
+    mixed_all<ORDER, T>(ld, ALP, ihxy, ihxz, ihyz, dd[1], dd[2], dd[4]);
     const T em4phi = t_exp<T>(T(-4) * phi);
     // A~^i_j, A~^ij and A~_ij A~^ij
     T Aud[3][3];
@@ -541,9 +560,7 @@ __device__ __forceinline__ void point_rhs(const L& ld, const Sp& sp,
     dd[3] = d2[1];
     dd[5] = d2[2];
     BSSN_PHASE();
-    dd[1] = mixed<ORDER, T>(ld, BETX + k, 0, 1, ihxy);
-    dd[2] = mixed<ORDER, T>(ld, BETX + k, 0, 2, ihxz);
-    dd[4] = mixed<ORDER, T>(ld, BETX + k, 1, 2, ihyz);
+    mixed_all<ORDER, T>(ld, BETX + k, ihxy, ihxz, ihyz, dd[1], dd[2], dd[4]);
     Tg[k] += gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
              T(2) * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]);
     Tg[k] += Gd[0] * db[0] + Gd[1] * db[1] + Gd[2] * db[2];
