@@ -1,12 +1,22 @@
 """Benchmark of the fused BSSN RHS + RK4 path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bl1-128]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bl2-384-o8]
 
 One "step" is one classical RK4 step (four fused stage launches) over the
 whole grid.  The timed region covers exactly K steps with inputs resident in
 HBM, bracketed by device synchronisations; HIP events recorded on the launch
 stream around every stage give the average kernel duration used for the
 roofline.  Prints ONE JSON line.
+
+The default run's headline is the largest single-grid workload, two
+Brill-Lindquist punctures on 384^3 + 5 ghosts with 8th-order differences:
+`value` is its FP64 rate, `mixed` the mixed-precision one, `roofline` the
+FP64 stage kernel against 8 TB/s (and against a 4 GiB device copy timed in
+the same run), `cpu_baseline` the FP64 oracle on the host cores (model,
+thread count, one-thread rate).  `workloads` adds the 256^3 and 128^3
+grids (FP64 and mixed; on 128^3 also the constraint norms after 100 RK4
+steps) and the 256 uneven patches (batched against one launch per patch);
+`extras` times the steps around the path on the 128^3 grid.
 
 Profiling support (the summaries under profiles/ are made this way):
     rocprofv3 --kernel-trace --stats --output-format csv -d D -o run \
@@ -346,49 +356,71 @@ def time_multipole(B, torch, g, reps=10):
             "lmax": lmax, "spin": -2, "radius": radius}
 
 
-def cpu_baseline(name, target_s=15.0):
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(name, target_s=15.0, width=128):
     """The oracle on the host cores over a bounded sample of the workload:
-    a z-slab of the same grid (same data, static ghosts taken from the full
-    grid), whole RK4 steps.  A probe slab of two planes per thread (the
-    oracle's loops are parallel over planes) sets the slab thickness (and,
-    when the whole grid is quicker than target_s, the step count) so that
-    the sample takes about target_s."""
+    a width x width x nz box of the same grid around its centre (same data,
+    static ghosts taken from the full grid's initial data), whole RK4 steps,
+    with as many threads as this process may run on.  The oracle's loops are
+    parallel over z planes, so nz is a multiple of the thread count: a probe
+    of one plane per thread sets it so that the sample takes about target_s.
+    One thread on a one-plane box gives the single-core rate."""
     import numpy as np
     from oracle import oracle as O
     from paper_1111_3344_amd import inputs as I
     n, lo, hi, gh, masses, centres, order, dt, desc = WORKLOADS[name]
     h = (hi - lo) / n
+    w = min(width, n)
     prm = O.params(fd_order=order)
+    cores = len(os.sched_getaffinity(0))
+    O.set_num_threads(cores)
+    threads = O.num_threads()
 
-    def slab(nz):
-        z0 = n // 2 - nz // 2
-        g = I.GridSpec((n, n, nz), gh, (h, h, h),
-                       (lo + 0.5 * h, lo + 0.5 * h, lo + 0.5 * h + z0 * h),
-                       I.BC_STATIC)
+    def box(nz):
+        x0, z0 = n // 2 - w // 2, n // 2 - nz // 2
+        g = I.GridSpec((w, w, nz), gh, (h, h, h),
+                       (lo + (0.5 + x0) * h, lo + (0.5 + x0) * h,
+                        lo + (0.5 + z0) * h), I.BC_STATIC)
         u = (I.brill_lindquist(g, masses, centres) if masses else
              I.minkowski_noise(g))
         return g, u
 
-    g, u = slab(min(n, 2 * O.num_threads()))
-    O.rk4_step(g, prm, dt, u)  # thread start-up outside the probe
-    t0 = time.perf_counter()
-    O.rk4_step(g, prm, dt, u)
-    rate = g.npoints / (time.perf_counter() - t0)
-    nz = int(max(1, min(n, round(target_s * rate / (n * n)))))
-    steps = 1
-    if nz == n:
-        steps = int(max(1, round(target_s * rate / (n * n * n))))
-    g, u = slab(nz)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        u = O.rk4_step(g, prm, dt, u)
-    t = time.perf_counter() - t0
-    pts = g.npoints * steps
-    return {"value": pts / t, "unit": "grid-point updates/s",
-            "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{steps} RK4 step(s) of the FP64 oracle on a "
-                      f"{n}x{n}x{nz} z-slab of {name} ({pts} point updates, "
-                      f"{t:.1f} s)"}
+    def rate(g, u, steps=1):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            u = O.rk4_step(g, prm, dt, u)
+        t = time.perf_counter() - t0
+        return g.npoints * steps / t, t
+
+    g, u = box(threads)
+    r0, _ = rate(g, u)
+    nz = threads * int(max(1, round(target_s * r0 / (w * w * threads))))
+    nz = min(nz, n)
+    g, u = box(nz)
+    r, t = rate(g, u)
+    O.set_num_threads(1)
+    g1, u1 = box(1)
+    r1, t1 = rate(g1, u1)
+    O.set_num_threads(cores)
+    return {"value": r, "unit": "grid-point updates/s",
+            "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "one_thread_value": r1,
+            "sample": f"1 RK4 step of the FP64 oracle on a {w}x{w}x{nz} box "
+                      f"at the centre of {name} ({g.npoints} point updates, "
+                      f"{t:.1f} s, {threads} threads); one thread: 1 step "
+                      f"on a {w}x{w}x1 box ({t1:.1f} s)"}
 
 
 # ---- rocprofv3 summaries ------------------------------------------------------
@@ -676,14 +708,122 @@ def accuracy(B, torch, name, steps=None, r_exc=1.0):
             "r_exc": r_exc if centres else None, **res}
 
 
+def run_grid(B, torch, name, steps, warmup, mixed=True):
+    """FP64 (and mixed-precision) RK4 steps of a single-grid workload:
+    wall-clock updates/s and the HIP-event duration of every stage kernel."""
+    g, u, order, dt, desc = build_state(name)
+    N = g.npoints
+    res = {}
+    for label, prec in (("f64", B.BSSN_FP64), ("mixed", B.BSSN_MIXED)):
+        if label == "mixed" and not mixed:
+            continue
+        prm = B.Params(fd_order=order, precision=prec)
+        wall, per_stage = time_gpu(B, torch, g, u, prm, dt, steps, warmup)
+        kern_ms = sum(per_stage)
+        ach = sum(b * N for b in STAGE_BYTES) / (kern_ms * 1e-3) / 1e9
+        res[label] = {"value": N * steps / wall,
+                      "ms_per_step": 1e3 * wall / steps,
+                      "stage_kernel_ms": [round(x, 4) for x in per_stage],
+                      "achieved_gbs": ach}
+    return g, u, order, dt, desc, res
+
+
+def grid_summary(res):
+    """Compact FP64 / mixed figures of run_grid for a secondary line."""
+    out = {}
+    for label, r in res.items():
+        out[label] = {"value": r["value"],
+                      "ms_per_step": round(r["ms_per_step"], 3),
+                      "hbm_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                      "stage_kernel_ms": r["stage_kernel_ms"]}
+    return out
+
+
+COPY_BYTES = 4 << 30
+
+
+def copy_bandwidth(torch, nbytes=COPY_BYTES, reps=5):
+    """HBM bandwidth of a plain device-to-device copy of nbytes (read +
+    write counted), best of reps, on the same GPU in the same run."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
+def constraint_norms_after(B, torch, name, steps, r_exc=1.0):
+    """Hamiltonian and momentum constraint norms of a workload after
+    `steps` FP64 RK4 steps from its initial data: RMS over every interior
+    point, and over the points farther than r_exc from each puncture."""
+    g, u, order, dt, desc = build_state(name)
+    centres = WORKLOADS[name][5]
+    prm = B.Params(fd_order=order)
+    du = torch.from_numpy(u).to("cuda")
+    a, b, acc = du.clone(), du.clone(), torch.zeros_like(du)
+    out = {"steps": steps, "t": steps * dt, "precision": "f64"}
+    for k in range(steps + 1):
+        if k in (0, steps):
+            for key, c, r in (("all", (), 0.0), ("masked", centres, r_exc)):
+                n = torch.zeros(8, dtype=torch.float64, device="cuda")
+                B.bssn_constraints(g, prm, du, n, centres=c, r_exc=r)
+                v = n.cpu().numpy()
+                out[f"{key}_t{'0' if k == 0 else 'end'}"] = {
+                    "H_rms": float(v[0]), "H_max": float(v[1]),
+                    "M_rms": float(v[2]), "points": int(v[6]),
+                    "nonfinite": int(v[7])}
+        if k < steps:
+            B.rk4_step(g, prm, dt, du, a, b, acc)
+    torch.cuda.synchronize()
+    out["r_exc"] = r_exc
+    del du, a, b, acc
+    torch.cuda.empty_cache()
+    return out
+
+
+def extras(B, torch, name, order):
+    """The steps around the path, timed on a workload's grid: radiative
+    boundary, ADM->BSSN conversion, refinement glue, multipole and
+    Berger-Oliger stepping."""
+    from paper_1111_3344_amd import inputs as I
+    wl = WORKLOADS[name]
+    g, u, order, dt, desc = build_state(name)
+    out = {"grid": name,
+           "radiative_bc": time_radiative(B, torch, g, u,
+                                          B.Params(fd_order=order)),
+           "adm_to_bssn": time_from_adm(B, torch, g, wl[4], wl[5], order),
+           "amr_glue": time_amr_glue(B, torch, g),
+           "multipole": time_multipole(B, torch, g),
+           "amr_berger_oliger": time_amr_step(B, torch, g, wl, order),
+           "amr_berger_oliger_mixed": time_amr_step(
+               B, torch, g, wl, order, precision=B.BSSN_MIXED)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="bl1-128", choices=list(WORKLOADS))
+    ap.add_argument("--workload", default="bl2-384-o8",
+                    choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline workload (no secondary "
+                         "workloads, extras or copy measurement)")
     ap.add_argument("--path", default="auto", choices=["auto", "direct"],
                     help="kernel: LDS-pipelined (auto) or direct-load")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -715,8 +855,9 @@ def main():
                     else B.BSSN_PATH_AUTO)
     if args.workload == "patches256":
         r = batched(B, torch, args.steps, args.warmup)
-        print(json.dumps({"workload": WORKLOADS["patches256"][8], "steps": args.steps,
-                          "warmup": args.warmup, **r}), flush=True)
+        print(json.dumps({"workload": WORKLOADS["patches256"][8],
+                          "steps": args.steps, "warmup": args.warmup, **r}),
+              flush=True)
         return
     if args.accuracy:
         print(json.dumps(accuracy(B, torch, args.workload)), flush=True)
@@ -729,23 +870,11 @@ def main():
                           "amr_glue": time_amr_glue(B, torch, gg)}),
               flush=True)
         return
-    g, u, order, dt, desc = build_state(args.workload)
+    g, u, order, dt, desc, res = run_grid(B, torch, args.workload,
+                                          args.steps, args.warmup,
+                                          mixed=not args.no_mixed)
+    del u
     N = g.npoints
-    res = {}
-    for label, prec in (("f64", B.BSSN_FP64), ("mixed", B.BSSN_MIXED)):
-        if label == "mixed" and args.no_mixed:
-            continue
-        prm = B.Params(fd_order=order, precision=prec)
-        wall, per_stage = time_gpu(B, torch, g, u, prm, dt, args.steps,
-                                   args.warmup)
-        kern_ms = sum(per_stage)
-        ach = sum(b * N for b in STAGE_BYTES) / (kern_ms * 1e-3) / 1e9
-        res[label] = {
-            "value": N * args.steps / wall,
-            "ms_per_step": 1e3 * wall / args.steps,
-            "stage_kernel_ms": [round(x, 4) for x in per_stage],
-            "achieved_gbs": ach,
-        }
     if args.calibrate_copy:
         calibrate_copy(torch)
     f = res["f64"]
@@ -770,8 +899,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "interior_points": N,
-                   "fd_order": order, "dt": dt},
+        "config": {"workload": desc, "name": args.workload,
+                   "interior_points": N, "fd_order": order, "dt": dt},
         "roofline": {"bound": "hbm", "achieved": round(f["achieved_gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(f["achieved_gbs"] / HBM_PEAK_GBS, 4),
@@ -800,7 +929,8 @@ def main():
                         "roofline_frac": round(m["achieved_gbs"] /
                                                HBM_PEAK_GBS, 4),
                         "achieved_gbs": round(m["achieved_gbs"], 1),
-                        "stage_kernel_ms": m["stage_kernel_ms"]}
+                        "stage_kernel_ms": m["stage_kernel_ms"],
+                        "speedup_vs_f64": round(m["value"] / f["value"], 4)}
         if lds:
             out["mixed"]["kernels"] = (
                 f"k_stage_lds_f32<{order}> (FP32 tiles) then "
@@ -818,20 +948,28 @@ def main():
                 if kv and t + "avg_launch_us" in kv:
                     out["mixed"][t[6:] + "profiled_avg_launch_us"] = float(
                         kv[t + "avg_launch_us"])
-    if g.bc == 0:  # static grid: its ghost layers as radiative boundary
-        out["radiative_bc"] = time_radiative(B, torch, g, u,
-                                             B.Params(fd_order=order))
-        wl = WORKLOADS[args.workload]
-        if g.npoints <= 256 ** 3:  # initial conversion of the same data
-            out["adm_to_bssn"] = time_from_adm(B, torch, g, wl[4], wl[5],
-                                               order)
-        if g.npoints <= 160 ** 3:  # refinement glue on this grid
-            out["amr_glue"] = time_amr_glue(B, torch, g)
-        out["multipole"] = time_multipole(B, torch, g)
-        if g.npoints <= 160 ** 3:
-            out["amr_berger_oliger"] = time_amr_step(B, torch, g, wl, order)
-            out["amr_berger_oliger_mixed"] = time_amr_step(
-                B, torch, g, wl, order, precision=B.BSSN_MIXED)
+    if not args.no_extra:
+        cp = copy_bandwidth(torch)
+        out["copy"] = {"gbs": round(cp, 1), "bytes": COPY_BYTES,
+                       "what": "device-to-device copy (read + write), best "
+                               "of 5, same GPU and run"}
+        out["roofline"]["frac_of_copy"] = round(f["achieved_gbs"] / cp, 4)
+        if "mixed" in out:
+            out["mixed"]["frac_of_copy"] = round(
+                res["mixed"]["achieved_gbs"] / cp, 4)
+        wk = {}
+        for name in ("bl2-256", "bl1-128"):
+            if name == args.workload:
+                continue
+            *_, r = run_grid(B, torch, name, args.steps, args.warmup,
+                             mixed=not args.no_mixed)
+            wk[name] = {"workload": WORKLOADS[name][8], **grid_summary(r)}
+        wk.setdefault("bl1-128", {})["constraints_100_steps"] = \
+            constraint_norms_after(B, torch, "bl1-128", 100)
+        wk["patches256"] = {"workload": WORKLOADS["patches256"][8],
+                            **batched(B, torch, args.steps, args.warmup)}
+        out["workloads"] = wk
+        out["extras"] = extras(B, torch, "bl1-128", 4)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

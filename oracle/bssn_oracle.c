@@ -810,3 +810,6 @@ int oracle_point_ops(const oracle_grid* g, const oracle_params* P,
 
 /* Number of OpenMP threads the oracle's parallel loops use. */
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+
+/* Number of OpenMP threads for the following parallel loops (n >= 1). */
+void oracle_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

@@ -47,6 +47,8 @@ def lib():
         _lib.oracle_constraints.argtypes = [g, p, d, d, d, d, d, ctypes.c_int,
                                             ctypes.c_double, d]
         _lib.oracle_num_threads.restype = ctypes.c_int
+        _lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        _lib.oracle_set_num_threads.restype = None
         _lib.oracle_point_ops.argtypes = [g, p, d, ctypes.c_int,
                                           P(ctypes.c_int32), d, d]
     return _lib
@@ -159,3 +161,8 @@ def point_ops(grid, prm, u, slot, p, beta=(1.0, 1.0, 1.0)):
 
 def num_threads():
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the oracle's parallel loops from now on."""
+    lib().oracle_set_num_threads(int(n))
