@@ -170,6 +170,23 @@ int bssn_constraints(const bssn_grid* grid, const bssn_params* params,
                      const double* centres, int ncent, double r_exc,
                      double* norms, void* stream);
 
+/* bssn_constraints for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, validation, kernels and results (bitwise) as
+ * bssn_constraints; the per-block partial norms go to a fixed device array
+ * of the library (16 MiB per GPU, held until the process ends) instead of
+ * a workspace the library allocates.  It calls no allocating routine.
+ * Limit: grids of at most 262,144 constraint blocks (one block per 64 x 4
+ * points of a plane, 32 x 8 when n_x <= 32; a 384^3 grid needs 221,184);
+ * larger grids return BSSN_EINVAL before anything is enqueued.  Calls on
+ * one GPU share the array: calls that overlap in time on one GPU (other
+ * streams, other host threads) race and must be ordered by the caller.
+ * Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED, BSSN_EHIP. */
+int bssn_constraints_noalloc(const bssn_grid* grid, const bssn_params* params,
+                             const double* u, double* H, double* M, double* G,
+                             const double* centres, int ncent, double r_exc,
+                             double* norms, void* stream);
+
 /* Initial conversion from the ADM variables to the BSSN state (section
  * "Spacetime Curvature Evolution", initial conditions): by the definitions
  *   phi = ln(det g)/12, gt_ij = e^{-4 phi} g_ij, K = g^ij K_ij,

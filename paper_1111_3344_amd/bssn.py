@@ -104,6 +104,9 @@ def lib():
         L.bssn_constraints.argtypes = [g, p, vp, vp, vp, vp,
                                        P(ctypes.c_double), ctypes.c_int,
                                        ctypes.c_double, vp, vp]
+        L.bssn_constraints_noalloc.argtypes = [g, p, vp, vp, vp, vp,
+                                       P(ctypes.c_double), ctypes.c_int,
+                                       ctypes.c_double, vp, vp]
         L.bssn_mixed_tile_count.argtypes = [g, p, vp, P(ctypes.c_int64),
                                             P(ctypes.c_int64), vp]
         L.bssn_from_adm.argtypes = [g, p, vp, vp, vp]
@@ -240,6 +243,19 @@ def bssn_constraints(grid, params, u, norms, H=None, M=None, G=None,
         ptr(grid, u), ptr(grid, H, 1), ptr(grid, M, 3), ptr(grid, G, 3),
         arr,
         len(flat) // 3, float(r_exc), ctypes.c_void_p(norms.data_ptr()),
+        _stream(stream)))
+
+
+def bssn_constraints_noalloc(grid, params, u, norms, H=None, M=None, G=None,
+                             centres=(), r_exc=0.0, stream=None):
+    """bssn_constraints without device allocation (the library's fixed
+    partials array; grids of at most 262,144 constraint blocks)."""
+    flat = [float(v) for c in centres for v in c]
+    arr = (ctypes.c_double * max(1, len(flat)))(*flat)
+    _check(lib().bssn_constraints_noalloc(
+        ctypes.byref(c_grid(grid)), ctypes.byref(_params(params)),
+        ptr(grid, u), ptr(grid, H, 1), ptr(grid, M, 3), ptr(grid, G, 3),
+        arr, len(flat) // 3, float(r_exc), ctypes.c_void_p(norms.data_ptr()),
         _stream(stream)))
 
 

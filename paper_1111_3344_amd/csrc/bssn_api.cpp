@@ -358,6 +358,45 @@ int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
 
 // ---- workspaces that live until the process ends ---------------------------------
 namespace bssn {
+// Validation of the bssn_constraints arguments and the kernels' view of them.
+int constraint_args(const bssn_grid* grid, const bssn_params* params,
+                    const double* u, double* H, double* M, double* G,
+                    const double* centres, int ncent, double r_exc,
+                    const double* norms, ConstraintArgs* A) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  if ((rc = check_grid(grid, params->fd_order))) return rc;
+  if (!u || !norms) return fail(BSSN_EINVAL, "u and norms must be non-NULL");
+  if (ncent < 0 || ncent > 16)
+    return fail(BSSN_EINVAL, "ncent = %d outside 0..16", ncent);
+  if (ncent > 0 && !centres)
+    return fail(BSSN_EINVAL, "centres is NULL with ncent > 0");
+  if (std::isnan(r_exc)) return fail(BSSN_EINVAL, "r_exc is NaN");
+  const double* outs[3] = {H, M, G};
+  for (const double* o : outs)
+    if (o && o == u) return fail(BSSN_EINVAL, "outputs must not alias u");
+  *A = ConstraintArgs{};
+  A->u = u;
+  A->H = H;
+  A->M = M;
+  A->Gc = G;
+  for (int a = 0; a < 3; ++a) {
+    A->n[a] = grid->n[a];
+    A->origin[a] = grid->origin[a];
+    A->h[a] = grid->h[a];
+  }
+  A->ghost = grid->ghost;
+  A->sy = int32_t(grid->sy);
+  A->sz = int32_t(grid->sz);
+  A->sf = grid->sf;
+  A->periodic = grid->bc == BSSN_BC_PERIODIC;
+  A->ncent = ncent;
+  for (int c = 0; c < ncent; ++c)
+    for (int a = 0; a < 3; ++a) A->centres[c][a] = centres[3 * c + a];
+  A->r_exc = r_exc;
+  return BSSN_OK;
+}
+
 namespace {
 struct DeviceWs {
   double* partials = nullptr;
@@ -385,37 +424,10 @@ int bssn_constraints(const bssn_grid* grid, const bssn_params* params,
                      const double* u, double* H, double* M, double* G,
                      const double* centres, int ncent, double r_exc,
                      double* norms, void* stream) {
-  int rc = check_params(params);
-  if (rc) return rc;
-  if ((rc = check_grid(grid, params->fd_order))) return rc;
-  if (!u || !norms) return fail(BSSN_EINVAL, "u and norms must be non-NULL");
-  if (ncent < 0 || ncent > 16)
-    return fail(BSSN_EINVAL, "ncent = %d outside 0..16", ncent);
-  if (ncent > 0 && !centres)
-    return fail(BSSN_EINVAL, "centres is NULL with ncent > 0");
-  if (std::isnan(r_exc)) return fail(BSSN_EINVAL, "r_exc is NaN");
-  const double* outs[3] = {H, M, G};
-  for (const double* o : outs)
-    if (o && o == u) return fail(BSSN_EINVAL, "outputs must not alias u");
   ConstraintArgs A{};
-  A.u = u;
-  A.H = H;
-  A.M = M;
-  A.Gc = G;
-  for (int a = 0; a < 3; ++a) {
-    A.n[a] = grid->n[a];
-    A.origin[a] = grid->origin[a];
-    A.h[a] = grid->h[a];
-  }
-  A.ghost = grid->ghost;
-  A.sy = int32_t(grid->sy);
-  A.sz = int32_t(grid->sz);
-  A.sf = grid->sf;
-  A.periodic = grid->bc == BSSN_BC_PERIODIC;
-  A.ncent = ncent;
-  for (int c = 0; c < ncent; ++c)
-    for (int a = 0; a < 3; ++a) A.centres[c][a] = centres[3 * c + a];
-  A.r_exc = r_exc;
+  int rc = constraint_args(grid, params, u, H, M, G, centres, ncent, r_exc,
+                           norms, &A);
+  if (rc) return rc;
   DeviceWs* ws = nullptr;
   if ((rc = device_ws(&ws))) return rc;
   const size_t nb = size_t(constraint_blocks(A));

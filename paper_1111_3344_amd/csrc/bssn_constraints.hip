@@ -15,6 +15,9 @@
 // result does not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
+#include "bssn_api_internal.h"
 #include "bssn_kernels.h"
 #include "bssn_stage.h"
 
@@ -470,3 +473,70 @@ hipError_t launch_tile_count(const Patch& P, double thr, int lds,
 }
 
 }  // namespace bssn
+
+// ---- constraints without allocation ---------------------------------------------
+// The per-block partial norms of bssn_constraints_noalloc live in this
+// file-scope device array: kNoAllocRecords records of 8 doubles (16 MiB),
+// which covers grids of up to 262,144 constraint blocks (a 384^3 grid needs
+// 221,184).  Each GPU holds its own copy for the life of the process.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): it uses the device address that
+// hipGetSymbolAddress returns, once per device, with that device current.
+namespace bssn {
+constexpr int kNoAllocRecords = 1 << 18;
+static __device__ __align__(256) double scratch[size_t(kNoAllocRecords) * 8];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch` (set up on the first
+// call on the device).
+int scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(BSSN_EUNSUPPORTED, "device %d beyond the %d the library "
+                "tracks", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return BSSN_OK;
+}
+}  // namespace
+}  // namespace bssn
+
+extern "C" int bssn_constraints_noalloc(const bssn_grid* grid,
+                                        const bssn_params* params,
+                                        const double* u, double* H,
+                                        double* M, double* G,
+                                        const double* centres, int ncent,
+                                        double r_exc, double* norms,
+                                        void* stream) {
+  using namespace bssn;
+  ConstraintArgs A{};
+  int rc = constraint_args(grid, params, u, H, M, G, centres, ncent, r_exc,
+                           norms, &A);
+  if (rc) return rc;
+  const long nb = constraint_blocks(A);
+  if (nb > kNoAllocRecords)
+    return fail(BSSN_EINVAL, "the grid needs %ld partial records; the "
+                "allocation-free constraints hold at most %d (a 384^3 grid "
+                "needs 221184)", nb, kNoAllocRecords);
+  double* part = nullptr;
+  if ((rc = scratch_address(&part))) return rc;
+  // every record a launch reads is written by the same launch: nothing to
+  // clear
+  const hipError_t e = launch_constraints(A, params->fd_order, part,
+                                          kNoAllocRecords, norms,
+                                          (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "bssn_constraints_noalloc launch");
+  return BSSN_OK;
+}

@@ -292,3 +292,22 @@ def test_batch_plan_validation():
     assert L.batch_patches(None, 1, None) == B.BSSN_EINVAL
     assert L.batch_patches_unbatched(None, 1, None) == B.BSSN_EINVAL
     assert L.batch_patches_describe(None, 0, None) == B.BSSN_EINVAL
+
+
+def test_constraints_noalloc_rejects_oversize_grid():
+    """The allocation-free constraints hold partial norms for at most
+    262,144 blocks: a 512^3 grid (8 x 128 x 512 blocks) is rejected on the
+    host before anything touches a device (fake device pointers)."""
+    g = I.cell_centred(512, -1, 1, 3)
+    norms = (ctypes.c_double * 8)()
+    rc = B.lib().bssn_constraints_noalloc(
+        ctypes.byref(B.c_grid(g)), ctypes.byref(B.Params().c()),
+        ctypes.c_void_p(64), None, None, None, None, 0, 0.0,
+        ctypes.c_void_p(128), None)
+    assert rc == B.BSSN_EINVAL
+    assert "262144" in B.bssn_last_error()
+    # the shared argument checks still apply
+    rc = B.lib().bssn_constraints_noalloc(
+        ctypes.byref(B.c_grid(g)), ctypes.byref(B.Params().c()), None, None,
+        None, None, None, 0, 0.0, ctypes.c_void_p(128), None)
+    assert rc == B.BSSN_EINVAL
