@@ -356,6 +356,36 @@ def time_multipole(B, torch, g, reps=10):
             "lmax": lmax, "spin": -2, "radius": radius}
 
 
+PSI4_BYTES = 128  # phi, gt_ij, K, At_ij in (14 slots), Re and Im out
+
+
+def time_psi4(B, torch, g, u_host, order, reps=10):
+    """bssn_psi4 over the whole grid (tetrad centred a little off the
+    origin), HIP events on the launch stream; algorithmic bytes 128 per
+    interior point."""
+    du = torch.from_numpy(u_host).to("cuda")
+    out = torch.zeros(g.off0 + 2 * g.sf, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    centre = (0.013, -0.021, 0.007)
+    B.bssn_psi4(g, order, du, out, centre, stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        B.bssn_psi4(g, order, du, out, centre, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    finite = bool(torch.isfinite(out).all().item())
+    del du, out
+    torch.cuda.empty_cache()
+    gbs = g.npoints * PSI4_BYTES / (ms * 1e-3) / 1e9
+    return {"kernel": f"k_psi4<{order}>", "ms_per_call": round(ms, 4),
+            "points": g.npoints, "bytes_per_point": PSI4_BYTES,
+            "achieved_gbs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "finite": finite}
+
+
 def cpu_model():
     """The host CPU's model name (/proc/cpuinfo), or None."""
     try:
@@ -793,6 +823,13 @@ def constraint_norms_after(B, torch, name, steps, r_exc=1.0):
     return out
 
 
+def psi4_o8_state(I, wl):
+    """The workload's grid and data with the 5 ghost layers of order 8."""
+    n, lo, hi, gh, masses, centres = wl[:6]
+    g = I.cell_centred(n, lo, hi, 5)
+    return g, I.brill_lindquist(g, masses, centres)
+
+
 def extras(B, torch, name, order):
     """The steps around the path, timed on a workload's grid: radiative
     boundary, ADM->BSSN conversion, refinement glue, multipole and
@@ -806,6 +843,8 @@ def extras(B, torch, name, order):
            "adm_to_bssn": time_from_adm(B, torch, g, wl[4], wl[5], order),
            "amr_glue": time_amr_glue(B, torch, g),
            "multipole": time_multipole(B, torch, g),
+           "psi4": time_psi4(B, torch, g, u, order),
+           "psi4_o8": time_psi4(B, torch, *psi4_o8_state(I, wl), 8),
            "amr_berger_oliger": time_amr_step(B, torch, g, wl, order),
            "amr_berger_oliger_mixed": time_amr_step(
                B, torch, g, wl, order, precision=B.BSSN_MIXED)}
@@ -832,6 +871,9 @@ def main():
     ap.add_argument("--accuracy", action="store_true",
                     help="FP64 vs mixed runs of the workload for its step "
                          "count: field errors and constraint norms")
+    ap.add_argument("--psi4-only", action="store_true",
+                    help="only time bssn_psi4 (orders 4 and 8) on the "
+                         "workload's grid")
     ap.add_argument("--amr-glue-only", action="store_true",
                     help="only the refinement-glue timing on the workload's "
                          "grid (JSON line)")
@@ -861,6 +903,18 @@ def main():
         return
     if args.accuracy:
         print(json.dumps(accuracy(B, torch, args.workload)), flush=True)
+        return
+    if args.psi4_only:
+        from paper_1111_3344_amd import inputs as I
+        wl = WORKLOADS[args.workload]
+        g, u, order, dt, desc = build_state(args.workload)
+        print(json.dumps({"workload": args.workload,
+                          "psi4": time_psi4(B, torch, g, u, order),
+                          "psi4_o8": time_psi4(B, torch,
+                                               *psi4_o8_state(I, wl), 8)}),
+              flush=True)
+        if args.calibrate_copy:
+            calibrate_copy(torch)
         return
     if args.amr_glue_only:
         from paper_1111_3344_amd import inputs as I

@@ -250,6 +250,36 @@ int bssn_multipole(const bssn_grid* grid, const double* re, const double* im,
                    int ntheta, int nphi, double* work, double* coeffs,
                    void* stream);
 
+/* The Weyl scalar Psi_4 (section "Analysis", gravitational waves: the
+ * WeylScal4 module) at every interior point of a grid:
+ *   Psi_4 = C_abcd n^a mb^b n^c mb^d
+ * on the fiducial tetrad l, n = (u +- rhat)/sqrt2, m = (thetahat +
+ * i phihat)/sqrt2 (u the slice's unit normal; the spatial triad from
+ * phi~ = (-y, x, 0), r~ = (x, y, z) and theta~^i = sqrt(det g) g^ik eps_klm
+ * phi~^l r~^m, coordinates relative to `centre`, orthonormalised with the
+ * 3-metric by Gram-Schmidt in the order phi, r, theta), evaluated as the
+ * paper's projection of the Riemann tensor from the 3+1 data (vacuum: the
+ * Weyl tensor is the Riemann tensor).  The ADM metric and curvature come
+ * from the state by inverting the BSSN definitions,
+ * g_ij = e^{4 phi} gt_ij, K_ij = e^{4 phi}(At_ij + gt_ij K/3), and are
+ * differentiated with the centred stencils of `fd_order` (mixed second
+ * derivatives as products of first-derivative stencils); FP64 throughout.
+ *   fd_order  4 or 8; the grid's ghost width must cover order/2 (the ABI's
+ *             usual minimum, 3 or 5, is required)
+ *   u         device state buffer (reads phi, gt_ij, K, At_ij at every
+ *             point within order/2 of the interior)
+ *   centre    host, 3 coordinates: the origin of the tetrad's x^i
+ *   psi4      device, two slots in the grid's layout (element 0 of the
+ *             storage grid; slot 1 at +sf): Re Psi_4 and Im Psi_4 at the
+ *             interior points; ghost points are not written.  Must not
+ *             overlap u.  The output can go straight to bssn_multipole
+ *             (re = psi4, im = psi4 + sf) with spin -2.
+ * Points on the tetrad's axis (x = y = 0 relative to the centre) have no
+ * phi direction; their values are NaN.  One launch on `stream`.  Errors:
+ * BSSN_EINVAL, BSSN_EUNSUPPORTED, BSSN_EHIP. */
+int bssn_psi4(const bssn_grid* grid, int fd_order, const double* u,
+              const double* centre, double* psi4, void* stream);
+
 /* Radiative (Sommerfeld-type) outer boundary (section "Spacetime Curvature
  * Evolution", boundary conditions): the right-hand side on the ghost layers
  * of a static grid, which then become evolved boundary points.  Every

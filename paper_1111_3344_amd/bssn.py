@@ -125,6 +125,8 @@ def lib():
                                      ctypes.c_double, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      vp, vp, vp]
+        L.bssn_psi4.argtypes = [g, ctypes.c_int, vp, P(ctypes.c_double),
+                                vp, vp]
         L.bssn_radiative_rhs.argtypes = [g, P(ctypes.c_double),
                                          P(ctypes.c_double), ctypes.c_int,
                                          vp, vp, vp]
@@ -322,6 +324,16 @@ def bssn_multipole(grid, re, im, centre, radius, spin, lmax, ntheta, nphi,
 # condition propagates at sqrt(f alpha) = sqrt(2) near alpha = 1.
 RADIATIVE_X0 = tuple(1.0 if s in (1, 4, 6, 17) else 0.0 for s in range(25))
 RADIATIVE_V0 = tuple(2.0 ** 0.5 if s in (7, 17) else 1.0 for s in range(25))
+
+
+def bssn_psi4(grid, fd_order, u, out, centre=(0.0, 0.0, 0.0), stream=None):
+    """Psi_4 of state u at the interior points: Re in slot 0 and Im in slot 1
+    of out (a flat float64 device tensor of at least off0 + 2 sf elements,
+    grid layout)."""
+    c = (ctypes.c_double * 3)(*[float(v) for v in centre])
+    _check(lib().bssn_psi4(ctypes.byref(c_grid(grid)), int(fd_order),
+                           ptr(grid, u), c, ptr(grid, out, nslot=2),
+                           _stream(stream)))
 
 
 def bssn_radiative_rhs(grid, u, rhs, x0=RADIATIVE_X0, v0=RADIATIVE_V0,

@@ -15,7 +15,8 @@ LIB = os.path.join(HERE, "libbssn_hip.so")
 SOURCES = ["bssn_api.cpp", "bssn_rhs_o4.hip", "bssn_rhs_o8.hip",
            "bssn_constraints.hip", "bssn_batch.cpp",
            "bssn_batch_o4.hip", "bssn_batch_o8.hip", "bssn_radiative.hip", "bssn_adm.hip",
-           "bssn_amr_plan.cpp", "bssn_amr.hip", "bssn_multipole.hip"]
+           "bssn_amr_plan.cpp", "bssn_amr.hip", "bssn_multipole.hip",
+           "bssn_psi4.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]

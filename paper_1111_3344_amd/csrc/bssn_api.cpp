@@ -301,6 +301,42 @@ int bssn_multipole(const bssn_grid* grid, const double* re, const double* im,
   return BSSN_OK;
 }
 
+int bssn_psi4(const bssn_grid* grid, int fd_order, const double* u,
+              const double* centre, double* psi4, void* stream) {
+  if (fd_order != 4 && fd_order != 8)
+    return fail(BSSN_EINVAL, "fd_order = %d (4 or 8)", fd_order);
+  int rc = check_grid(grid, fd_order);
+  if (rc) return rc;
+  if (!u || !psi4 || !centre)
+    return fail(BSSN_EINVAL, "u, centre and psi4 must be non-NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(centre[a]))
+      return fail(BSSN_EINVAL, "centre[%d] is not finite", a);
+  // the two output slots [psi4, psi4 + 2 sf) must not overlap the state
+  // [u, u + 25 sf)
+  const uintptr_t o0 = (uintptr_t)psi4, o1 = o0 + 16 * (uintptr_t)grid->sf;
+  const uintptr_t u0 = (uintptr_t)u, u1 = u0 + 8 * (uintptr_t)grid->sf * 25;
+  if (o0 < u1 && u0 < o1)
+    return fail(BSSN_EINVAL, "psi4 overlaps the state u");
+  Psi4Args A{};
+  A.u = u;
+  A.out = psi4;
+  for (int a = 0; a < 3; ++a) {
+    A.n[a] = grid->n[a];
+    A.origin[a] = grid->origin[a];
+    A.h[a] = grid->h[a];
+    A.centre[a] = centre[a];
+  }
+  A.ghost = grid->ghost;
+  A.sy = grid->sy;
+  A.sz = grid->sz;
+  A.sf = grid->sf;
+  hipError_t e = launch_psi4(A, fd_order, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "bssn_psi4 launch");
+  g_err = "no error";
+  return BSSN_OK;
+}
+
 int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
                        const double* v0, int power, const double* u,
                        double* rhs, void* stream) {

@@ -164,6 +164,19 @@ inline int multipole_chunks(int ntheta, int nphi) {
 hipError_t launch_multipole(const MultipoleArgs& A, double* work,
                             double* coeffs, hipStream_t st);
 
+// The Weyl scalar Psi_4 (bssn_psi4): re and im at the interior points of
+// out (slots 0 and 1 of the grid's layout) from the state u.
+struct Psi4Args {
+  const double* u;
+  double* out;
+  int32_t n[3];
+  int32_t ghost;
+  int64_t sy, sz, sf;
+  double origin[3], h[3];
+  double centre[3];
+};
+hipError_t launch_psi4(const Psi4Args& A, int order, hipStream_t st);
+
 // Mesh-refinement glue (bssn_amr_*): ops built on the host, one per copied
 // ghost point or restricted coarse point.  dst and src are element offsets
 // from the slot-0 origin of the destination and source patch states.

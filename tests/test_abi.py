@@ -241,6 +241,31 @@ def test_multipole_validation():
     assert call(nph=4097) == B.BSSN_EINVAL
 
 
+def test_psi4_validation():
+    L = B.lib()
+    g = I.cell_centred(8, -1, 1, 3)
+    c = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    bad_c = (ctypes.c_double * 3)(0.0, 0.0, float("inf"))
+    base = 1 << 30
+
+    def call(order=4, u=base, out=base + 64 * g.sf, cen=c, grid=g):
+        return L.bssn_psi4(ctypes.byref(B.c_grid(grid)), order, P(u), cen,
+                           P(out), None)
+
+    assert call(order=6) == B.BSSN_EINVAL
+    assert call(order=8) == B.BSSN_EINVAL          # ghost 3 < 5
+    assert call(u=0) == B.BSSN_EINVAL
+    assert call(out=0) == B.BSSN_EINVAL
+    assert call(cen=None) == B.BSSN_EINVAL
+    assert call(cen=bad_c) == B.BSSN_EINVAL
+    # the two output slots may not overlap the 25 state slots
+    assert call(out=base + 8 * 24 * g.sf) == B.BSSN_EINVAL
+    assert "overlaps" in B.bssn_last_error()
+    assert call(out=base - 8 * g.sf) == B.BSSN_EINVAL
+    g8 = I.cell_centred(8, -1, 1, 5)
+    assert call(order=8, grid=g8, out=0) == B.BSSN_EINVAL  # reaches out=0
+
+
 def test_periodic_grid_must_cover_stencil():
     g = I.GridSpec((2, 8, 8), 3, (0.1,) * 3, (0,) * 3, I.BC_PERIODIC)
     assert _stage(B.c_grid(g), B.Params().c()) == B.BSSN_EINVAL
