@@ -153,6 +153,47 @@ def time_radiative(B, torch, g, u_host, prm, reps=20, warmup=2):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def time_radiative_step(B, torch, g, u_host, prm, steps=10, warmup=2):
+    """Whole RK4 steps with the radiative boundary evolved
+    (rk4_stage_radiative: shell right-hand side, fused interior stage,
+    boundary stage update per stage) against the same steps with static
+    ghosts (rk4_stage), HIP events on the launch stream."""
+    du = torch.from_numpy(u_host).to("cuda")
+    a, b, acc, k = (torch.zeros_like(du) for _ in range(4))
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, step in (("static", lambda: B.rk4_step(
+            g, prm, 0.03125, du, a, b, acc, stream)),
+                       ("radiative", lambda: B.rk4_step_radiative(
+                           g, prm, 0.03125, du, a, b, acc, k,
+                           stream=stream))):
+        du.copy_(torch.from_numpy(u_host))
+        a.copy_(du)
+        b.copy_(du)
+        acc.copy_(du)
+        for _ in range(warmup):
+            step()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / steps
+    finite = bool(torch.isfinite(du).all().item())
+    del du, a, b, acc, k
+    torch.cuda.empty_cache()
+    return {"kernels": "k_shell_rhs, k_stage_lds, k_radiative_stage per "
+                       "stage",
+            "ms_per_step_radiative": round(res["radiative"], 4),
+            "ms_per_step_static": round(res["static"], 4),
+            "overhead": round(res["radiative"] / res["static"] - 1.0, 4),
+            "updates_per_s_radiative": round(
+                g.npoints / (res["radiative"] * 1e-3), 1),
+            "finite": finite}
+
+
 ADM_BYTES_PER_POINT = 328  # 16 ADM values in, 25 BSSN values out (8 B each)
 
 
@@ -840,6 +881,8 @@ def extras(B, torch, name, order):
     out = {"grid": name,
            "radiative_bc": time_radiative(B, torch, g, u,
                                           B.Params(fd_order=order)),
+           "radiative_step": time_radiative_step(B, torch, g, u,
+                                                 B.Params(fd_order=order)),
            "adm_to_bssn": time_from_adm(B, torch, g, wl[4], wl[5], order),
            "amr_glue": time_amr_glue(B, torch, g),
            "multipole": time_multipole(B, torch, g),

@@ -306,6 +306,34 @@ int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
                        const double* v0, int power, const double* u,
                        double* rhs, void* stream);
 
+/* One RK4 stage of an evolution whose outer boundary is radiative (section
+ * "Spacetime Curvature Evolution", boundary conditions: the boundary points'
+ * right-hand side is integrated in time like the interior's).  The ghost
+ * layers of the static grid are evolved points: every storage point of
+ * u_out (and of acc) is written, the interior by the fused stage of
+ * rk4_stage, the ghost layers by the radiative right-hand side of
+ * bssn_radiative_rhs (x0, v0, power as there) put through the same stage
+ * update:
+ *   s = 0: acc = u_n + dt/6 k,  u_out = u_n + dt/2 k
+ *   s = 1: acc = acc + dt/3 k,  u_out = u_n + dt/2 k
+ *   s = 2: acc = acc + dt/3 k,  u_out = u_n + dt k
+ *   s = 3:                      u_out = acc + dt/6 k
+ * The boundary is carried outward from the interior right-hand side at the
+ * outermost layer of interior points, which this call evaluates in FP64
+ * (in either precision) into k.
+ *   stage, dt, u_n, u_s, acc, u_out  as rk4_stage (same aliasing rules)
+ *   k   device work buffer in the state layout (25 slots), aliasing no other
+ *       buffer; on return its outermost interior layer holds the interior
+ *       right-hand side there, everything else in it is untouched
+ * Needs a static grid whose coordinate origin is neither a ghost point nor
+ * on the outermost interior layer (r = 0 there).  Three launches on
+ * `stream`.  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED, BSSN_EHIP. */
+int rk4_stage_radiative(const bssn_grid* grid, const bssn_params* params,
+                        int stage, double dt, const double* x0,
+                        const double* v0, int power, const double* u_n,
+                        const double* u_s, double* acc, double* u_out,
+                        double* k, void* stream);
+
 /* Number of tiles a BSSN_MIXED evaluation of u runs in FP64 (tiles whose
  * minimum lapse over their points is below params->fp64_alpha_threshold)
  * and the total number of tiles.  Tiles are those of the kernel a stage on

@@ -125,6 +125,9 @@ def lib():
                                      ctypes.c_double, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      vp, vp, vp]
+        L.rk4_stage_radiative.argtypes = [
+            g, p, ctypes.c_int, ctypes.c_double, P(ctypes.c_double),
+            P(ctypes.c_double), ctypes.c_int, vp, vp, vp, vp, vp, vp]
         L.bssn_psi4.argtypes = [g, ctypes.c_int, vp, P(ctypes.c_double),
                                 vp, vp]
         L.bssn_radiative_rhs.argtypes = [g, P(ctypes.c_double),
@@ -324,6 +327,29 @@ def bssn_multipole(grid, re, im, centre, radius, spin, lmax, ntheta, nphi,
 # condition propagates at sqrt(f alpha) = sqrt(2) near alpha = 1.
 RADIATIVE_X0 = tuple(1.0 if s in (1, 4, 6, 17) else 0.0 for s in range(25))
 RADIATIVE_V0 = tuple(2.0 ** 0.5 if s in (7, 17) else 1.0 for s in range(25))
+
+
+def rk4_stage_radiative(grid, params, stage, dt, u_n, u_s, acc, u_out, k,
+                        x0=None, v0=None, power=2, stream=None):
+    """One RK4 stage with the radiative outer boundary evolved (k: a state-
+    sized work buffer)."""
+    x0 = RADIATIVE_X0 if x0 is None else x0
+    v0 = RADIATIVE_V0 if v0 is None else v0
+    cx = (ctypes.c_double * 25)(*[float(v) for v in x0])
+    cv = (ctypes.c_double * 25)(*[float(v) for v in v0])
+    _check(lib().rk4_stage_radiative(
+        ctypes.byref(c_grid(grid)), ctypes.byref(_params(params)), int(stage),
+        float(dt), cx, cv, int(power), ptr(grid, u_n), ptr(grid, u_s),
+        ptr(grid, acc), ptr(grid, u_out), ptr(grid, k), _stream(stream)))
+
+
+def rk4_step_radiative(grid, params, dt, u, a, b, acc, k, x0=None, v0=None,
+                       power=2, stream=None):
+    """One RK4 step of state u (in place) with the radiative boundary; a, b,
+    acc, k are state-sized work buffers."""
+    for s, (us, uo) in enumerate(((u, a), (a, b), (b, a), (a, u))):
+        rk4_stage_radiative(grid, params, s, dt, u, us, acc, uo, k, x0, v0,
+                            power, stream)
 
 
 def bssn_psi4(grid, fd_order, u, out, centre=(0.0, 0.0, 0.0), stream=None):

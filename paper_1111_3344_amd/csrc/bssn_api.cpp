@@ -337,37 +337,36 @@ int bssn_psi4(const bssn_grid* grid, int fd_order, const double* u,
   return BSSN_OK;
 }
 
-int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
-                       const double* v0, int power, const double* u,
-                       double* rhs, void* stream) {
-  int rc = check_grid(grid, 4);
-  if (rc) return rc;
+namespace {
+// Checks shared by the radiative entry points, and their kernel arguments.
+int radiative_args(const bssn_grid* grid, const double* x0, const double* v0,
+                   int power, const double* u, double* rhs, RadiativeArgs& A) {
   if (grid->bc != BSSN_BC_STATIC)
     return fail(BSSN_EINVAL, "the radiative boundary needs a static grid "
                 "(its ghost layers are the boundary points)");
   if (!x0 || !v0) return fail(BSSN_EINVAL, "x0 and v0 must be non-NULL");
-  if (!u || !rhs) return fail(BSSN_EINVAL, "u and rhs must be non-NULL");
-  if (u == rhs) return fail(BSSN_EINVAL, "rhs must not alias u");
   if (power < 0 || power > 16)
     return fail(BSSN_EINVAL, "power = %d outside 0..16", power);
   for (int s = 0; s < BSSN_NSLOT; ++s)
     if (!std::isfinite(x0[s]) || !std::isfinite(v0[s]) || v0[s] < 0.0)
       return fail(BSSN_EINVAL, "slot %d: x0 and v0 must be finite, v0 >= 0",
                   s);
-  // r = 0 at a boundary point would divide by zero: the coordinate origin
-  // must not be one of them
+  // r = 0 at a boundary point or at one of the interior points the
+  // boundary is carried from (the outermost interior layer) would divide by
+  // zero: the coordinate origin must be neither
   bool at[3];
-  bool inside = true;
+  bool deep = true;
   for (int a = 0; a < 3; ++a) {
     const double j = grid->ghost - grid->origin[a] / grid->h[a];
     const double jr = std::nearbyint(j);
     at[a] = std::fabs(j - jr) <= 1e-9 * (1.0 + std::fabs(j)) && jr >= 0 &&
             jr < grid->n[a] + 2.0 * grid->ghost;
-    inside = inside && jr >= grid->ghost && jr < grid->n[a] + grid->ghost;
+    deep = deep && jr > grid->ghost && jr < grid->n[a] + grid->ghost - 1;
   }
-  if (at[0] && at[1] && at[2] && !inside)
-    return fail(BSSN_EINVAL, "the coordinate origin is a boundary point");
-  RadiativeArgs A{};
+  if (at[0] && at[1] && at[2] && !deep)
+    return fail(BSSN_EINVAL, "the coordinate origin is a boundary point or "
+                "on the outermost interior layer");
+  A = RadiativeArgs{};
   A.u = u;
   A.rhs = rhs;
   for (int a = 0; a < 3; ++a) {
@@ -384,8 +383,72 @@ int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
     A.v0[s] = v0[s];
   }
   A.power = power;
+  return BSSN_OK;
+}
+}  // namespace
+
+int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
+                       const double* v0, int power, const double* u,
+                       double* rhs, void* stream) {
+  int rc = check_grid(grid, 4);
+  if (rc) return rc;
+  if (!u || !rhs) return fail(BSSN_EINVAL, "u and rhs must be non-NULL");
+  if (u == rhs) return fail(BSSN_EINVAL, "rhs must not alias u");
+  RadiativeArgs A;
+  if ((rc = radiative_args(grid, x0, v0, power, u, rhs, A))) return rc;
   hipError_t e = launch_radiative(A, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "bssn_radiative_rhs launch");
+  g_err = "no error";
+  return BSSN_OK;
+}
+
+int rk4_stage_radiative(const bssn_grid* grid, const bssn_params* params,
+                        int stage, double dt, const double* x0,
+                        const double* v0, int power, const double* u_n,
+                        const double* u_s, double* acc, double* u_out,
+                        double* k, void* stream) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  if ((rc = check_grid(grid, params->fd_order))) return rc;
+  if (stage < 0 || stage > 3)
+    return fail(BSSN_EINVAL, "stage = %d outside 0..3", stage);
+  if (!std::isfinite(dt)) return fail(BSSN_EINVAL, "dt is not finite");
+  if (!u_n || !u_s || !acc || !u_out || !k)
+    return fail(BSSN_EINVAL, "u_n, u_s, acc, u_out and k must be non-NULL");
+  if (u_out == u_s) return fail(BSSN_EINVAL, "u_out must not alias u_s");
+  if (acc == u_n || acc == u_s || acc == u_out)
+    return fail(BSSN_EINVAL, "acc must not alias any other buffer");
+  if (u_out == u_n && stage != 3)
+    return fail(BSSN_EINVAL, "u_out may alias u_n only at stage 3");
+  if (k == u_n || k == u_s || k == acc || k == u_out)
+    return fail(BSSN_EINVAL, "k must not alias any other buffer");
+  RadiativeArgs A;
+  if ((rc = radiative_args(grid, x0, v0, power, u_s, k, A))) return rc;
+  const hipStream_t st = (hipStream_t)stream;
+  const Gauge G = make_gauge(params);
+  // 1. the interior right-hand side at the radiative boundary's roots
+  Patch S = make_patch(grid);
+  S.u_s = u_s;
+  S.u_n = u_s;
+  S.acc = nullptr;
+  S.out = k;
+  S.dt = 0.0;
+  hipError_t e = launch_shell_rhs(S, G, params->fd_order, st);
+  if (e != hipSuccess) return hip_fail(e, "rk4_stage_radiative shell launch");
+  // 2. the fused stage at the interior points
+  Patch P = make_patch(grid);
+  P.u_s = u_s;
+  P.u_n = u_n;
+  P.acc = acc;
+  P.out = u_out;
+  P.dt = dt;
+  e = launch_stage(P, G, params->fd_order, 0, stage, params->precision, st);
+  if (e != hipSuccess) return hip_fail(e, "rk4_stage_radiative launch");
+  // 3. the boundary points: radiative right-hand side and stage update
+  RadStage R{u_n, acc, u_out, dt, stage};
+  e = launch_radiative_stage(A, R, st);
+  if (e != hipSuccess)
+    return hip_fail(e, "rk4_stage_radiative boundary launch");
   g_err = "no error";
   return BSSN_OK;
 }

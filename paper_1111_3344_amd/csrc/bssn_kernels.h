@@ -29,6 +29,16 @@ inline hipError_t launch_stage(const Patch& P, const Gauge& G, int order,
              : launch_stage_o4(P, G, periodic, stage, precision, path, nwg, st);
 }
 
+// FP64 right-hand side (P.out, state layout) at the outermost layer of
+// interior points of a static patch (the radiative boundary's roots).
+hipError_t launch_shell_rhs_o4(const Patch& P, const Gauge& G, hipStream_t st);
+hipError_t launch_shell_rhs_o8(const Patch& P, const Gauge& G, hipStream_t st);
+inline hipError_t launch_shell_rhs(const Patch& P, const Gauge& G, int order,
+                                   hipStream_t st) {
+  return order == 8 ? launch_shell_rhs_o8(P, G, st)
+                    : launch_shell_rhs_o4(P, G, st);
+}
+
 // One static patch with an explicit kernel variant (VAR_*); nwg bounds the
 // persistent launch of VAR_LDS.
 hipError_t launch_patch_o4(const Patch& P, const Gauge& G, int stage,
@@ -115,6 +125,20 @@ struct RadiativeArgs {
   int32_t power;
 };
 hipError_t launch_radiative(const RadiativeArgs& A, hipStream_t st);
+// The radiative boundary inside an RK4 stage: the same right-hand side at
+// every ghost point (from A.u = the stage input and A.rhs = a buffer whose
+// outermost interior layer holds the interior right-hand side), fed
+// straight into the stage update of that point (as the fused stage does for
+// interior points): acc and out at the ghost points.
+struct RadStage {
+  const double* u_n;
+  double* acc;
+  double* out;
+  double dt;
+  int32_t stage;
+};
+hipError_t launch_radiative_stage(const RadiativeArgs& A, const RadStage& S,
+                                  hipStream_t st);
 
 // ADM -> BSSN initial conversion (bssn_from_adm): adm holds 16 slots in
 // the state layout (g_ij, K_ij, alpha, beta^i); every slot of u is written

@@ -16,6 +16,11 @@ hipError_t launch_stage_o8(const Patch& P, const Gauge& G, int periodic,
                                                    st);
 }
 
+hipError_t launch_shell_rhs_o8(const Patch& P, const Gauge& G,
+                               hipStream_t st) {
+  return launch_shell_rhs_t<8>(P, G, st);
+}
+
 hipError_t launch_patch_o8(const Patch& P, const Gauge& G, int stage,
                            int precision, int variant, int nwg,
                            hipStream_t st) {

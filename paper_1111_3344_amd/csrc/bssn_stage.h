@@ -335,6 +335,64 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The right-hand side (FP64) at the outermost layer of interior points of a
+// static patch (the points whose stencils reach a ghost layer first): the
+// inward roots of the radiative boundary.  One thread per shell point,
+// numbered as the two end planes in z (whole), then in the other planes
+// the two end rows in y (whole), then the two ends of the remaining rows
+// (ends that coincide on a one-point-wide axis are taken once).
+struct ShellCount {
+  int64_t na, nb, nc;
+};
+__host__ __device__ inline ShellCount shell_count(const int32_t (&n)[3]) {
+  const int64_t nx = n[0], ny = n[1], nz = n[2];
+  const int64_t nzp = nz > 1 ? 2 : 1, nyr = ny > 1 ? 2 : 1,
+                nxe = nx > 1 ? 2 : 1;
+  const int64_t nzi = nz > 2 ? nz - 2 : 0, nyi = ny > 2 ? ny - 2 : 0;
+  return {nzp * nx * ny, nzi * nyr * nx, nzi * nyi * nxe};
+}
+
+template <int ORDER>
+__global__ void __launch_bounds__(256) k_shell_rhs(const Patch P,
+                                                   const Gauge G) {
+  const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const ShellCount c = shell_count(P.n);
+  const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+  int x, y, z;
+  if (t < c.na) {
+    const int64_t pl = t / (int64_t(nx) * ny), m = t % (int64_t(nx) * ny);
+    z = pl == 0 ? 0 : nz - 1;
+    y = int(m / nx);
+    x = int(m % nx);
+  } else if (t < c.na + c.nb) {
+    const int64_t u = t - c.na, row = u / nx;
+    const int nyr = ny > 1 ? 2 : 1;
+    x = int(u % nx);
+    z = 1 + int(row / nyr);
+    y = row % nyr == 0 ? 0 : ny - 1;
+  } else if (t < c.na + c.nb + c.nc) {
+    const int64_t u = t - c.na - c.nb;
+    const int nxe = nx > 1 ? 2 : 1;
+    const int64_t row = u / nxe;
+    x = u % nxe == 0 ? 0 : nx - 1;
+    y = 1 + int(row % (ny - 2));
+    z = 1 + int(row / (ny - 2));
+  } else {
+    return;
+  }
+  stage_point<ORDER, false, double>(P, G, ST_RHS, x, y, z);
+}
+
+template <int ORDER>
+hipError_t launch_shell_rhs_t(const Patch& P, const Gauge& G, hipStream_t st) {
+  const ShellCount c = shell_count(P.n);
+  const int64_t blocks = (c.na + c.nb + c.nc + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_shell_rhs<ORDER>), dim3(unsigned(blocks)), dim3(256),
+                     0, st, P, G);
+  return hipGetLastError();
+}
+
 // ---- host-side launch -------------------------------------------------------------
 // Workgroup shape of the direct kernel: bx x (256 / bx); bx = 0 picks it
 // from the patch width.

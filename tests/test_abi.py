@@ -241,6 +241,38 @@ def test_multipole_validation():
     assert call(nph=4097) == B.BSSN_EINVAL
 
 
+def test_rk4_stage_radiative_validation():
+    L = B.lib()
+    g = I.cell_centred(8, -1, 1, 3)
+    prm = B.Params().c()
+    x0 = (ctypes.c_double * 25)(*B.RADIATIVE_X0)
+    v0 = (ctypes.c_double * 25)(*B.RADIATIVE_V0)
+    bad_v = (ctypes.c_double * 25)(*([-1.0] + [1.0] * 24))
+
+    def call(stage=0, dt=0.1, cx=x0, cv=v0, power=2, un=1, us=1, acc=2,
+             out=3, k=4, grid=g):
+        return L.rk4_stage_radiative(
+            ctypes.byref(B.c_grid(grid)), ctypes.byref(prm), stage, dt, cx,
+            cv, power, P(un), P(us), P(acc), P(out), P(k), None)
+
+    assert call(stage=4) == B.BSSN_EINVAL
+    assert call(dt=float("inf")) == B.BSSN_EINVAL
+    assert call(k=0) == B.BSSN_EINVAL
+    assert call(k=2) == B.BSSN_EINVAL                 # k aliases acc
+    assert call(k=1) == B.BSSN_EINVAL                 # k aliases u_s
+    assert call(out=1) == B.BSSN_EINVAL               # u_out aliases u_s
+    assert call(acc=1) == B.BSSN_EINVAL
+    assert call(cv=bad_v) == B.BSSN_EINVAL
+    assert call(cx=None) == B.BSSN_EINVAL
+    assert call(power=17) == B.BSSN_EINVAL
+    gp = I.cell_centred(8, -1, 1, 3, I.BC_PERIODIC)
+    assert call(grid=gp) == B.BSSN_EINVAL
+    # the coordinate origin on the outermost interior layer: r = 0 at a root
+    go = I.GridSpec((6, 6, 6), 3, (0.5,) * 3, (0.0, -1.0, -1.0), I.BC_STATIC)
+    assert call(grid=go) == B.BSSN_EINVAL
+    assert "outermost interior layer" in B.bssn_last_error()
+
+
 def test_psi4_validation():
     L = B.lib()
     g = I.cell_centred(8, -1, 1, 3)
