@@ -254,19 +254,41 @@ def nested_hierarchy(g, nlevel=3):
     return hier
 
 
-def time_amr_step(B, torch, g, wl, order, steps=3, precision=None):
+def split_hierarchy(g, nlevel=3, k=2):
+    """nested_hierarchy with every level cut into k x k x k sibling patches
+    of n/k points per axis (same lattice, sharing faces): k^3 patches per
+    level, whose face ghosts come from their siblings."""
+    from paper_1111_3344_amd import inputs as I
+    out = []
+    for L, gr in nested_hierarchy(g, nlevel):
+        m = tuple(x // k for x in gr.n)
+        for cz in range(k):
+            for cy in range(k):
+                for cx in range(k):
+                    c = (cx, cy, cz)
+                    o = tuple(gr.origin[a] + c[a] * m[a] * gr.h[a]
+                              for a in range(3))
+                    out.append((L, I.GridSpec(m, gr.ghost, gr.h, o,
+                                              I.BC_STATIC)))
+    return out
+
+
+def time_amr_step(B, torch, g, wl, order, steps=3, precision=None,
+                  split=1, batched=True):
     """Berger-Oliger stepping (paper_1111_3344_amd.amr) of the workload's
-    punctures on three nested levels of its grid (nested_hierarchy): one
-    level-0 step = 1 + 2 + 4 level steps, a ghost fill per RK4 stage and
-    per level step, two restrictions.  One warm-up step, then `steps`
-    steps between device synchronisations (host clock)."""
+    punctures on three nested levels of its grid (nested_hierarchy, or with
+    split > 1 split_hierarchy: split^3 patches per level): one level-0 step
+    = 1 + 2 + 4 level steps, a ghost fill per RK4 stage and per level step,
+    two restrictions; a level's stages batched over its patches or one
+    launch per patch.  One warm-up step, then `steps` steps between device
+    synchronisations (host clock)."""
     from paper_1111_3344_amd import amr
     from paper_1111_3344_amd import inputs as I
-    hier = nested_hierarchy(g)
+    hier = nested_hierarchy(g) if split == 1 else split_hierarchy(g, k=split)
     u0 = [B.to_device(I.brill_lindquist(gr, wl[4], wl[5])) for _, gr in hier]
     prm = B.Params(fd_order=order,
                    precision=B.BSSN_FP64 if precision is None else precision)
-    drv = amr.BergerOliger(hier, prm, wl[7], u0)
+    drv = amr.BergerOliger(hier, prm, wl[7], u0, batched=batched)
     drv.step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -283,7 +305,11 @@ def time_amr_step(B, torch, g, wl, order, steps=3, precision=None):
             "level_steps_per_level0_step": level_steps,
             "fills_per_level0_step": 5 * (level_steps - 1),
             "updates_per_s": upd / (ms * 1e-3), "finite": ok,
-            "hierarchy": "3 nested levels of the workload grid, h, h/2, h/4"}
+            "hierarchy": "3 nested levels of the workload grid, h, h/2, h/4"
+                         + (f", each cut into {split ** 3} patches"
+                            if split > 1 else ""),
+            "level_stages": "batched over the level's patches" if batched
+                            else "one launch per patch"}
 
 
 AMR_FILL_BYTES = 232      # 32 B bookkeeping + 25 values written; reads below
@@ -890,7 +916,11 @@ def extras(B, torch, name, order):
            "psi4_o8": time_psi4(B, torch, *psi4_o8_state(I, wl), 8),
            "amr_berger_oliger": time_amr_step(B, torch, g, wl, order),
            "amr_berger_oliger_mixed": time_amr_step(
-               B, torch, g, wl, order, precision=B.BSSN_MIXED)}
+               B, torch, g, wl, order, precision=B.BSSN_MIXED),
+           "amr_berger_oliger_8patches": time_amr_step(
+               B, torch, g, wl, order, split=2),
+           "amr_berger_oliger_8patches_per_patch": time_amr_step(
+               B, torch, g, wl, order, split=2, batched=False)}
     return out
 
 

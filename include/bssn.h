@@ -385,9 +385,31 @@ int batch_patches_plan(int npatch, const bssn_grid* grids,
                        double* const* acc, const double* dt, int autotune,
                        bssn_batch_plan** plan, void* stream);
 
+/* batch_patches_plan whose steps put u_{n+1} into u_new[p] instead of
+ * u[p] (stage 3 writes u_new; u[p] keeps u_n): the form a stepper needs
+ * that keeps earlier time levels, such as Berger-Oliger subcycling (the
+ * paper's adaptive mesh refinement: a level's patches step together,
+ * their ghost points filled between stages).  u_new[p] may equal u[p];
+ * it must not alias a, b or acc.  Same validation and errors, plus
+ * BSSN_EINVAL for a NULL u_new. */
+int batch_patches_plan_out(int npatch, const bssn_grid* grids,
+                           const bssn_params* params, double* const* u,
+                           double* const* u_new, double* const* a,
+                           double* const* b, double* const* acc,
+                           const double* dt, int autotune,
+                           bssn_batch_plan** plan, void* stream);
+
 /* Advance every patch of the plan by nsteps RK4 steps (one graph launch per
  * step on `stream`).  Returns BSSN_ESTALE if the plan was invalidated. */
 int batch_patches(bssn_batch_plan* plan, int nsteps, void* stream);
+
+/* One RK4 stage (0..3) of every patch of the plan: the plan's launches of
+ * that stage, replayed from their own graph on `stream`.  Stages 0..3 in
+ * order make one step, as batch_patches does; between them the caller may
+ * rewrite the ghost points of the next stage's input (u, a, b, a for stages
+ * 0..3), as a refinement hierarchy does.  Errors: BSSN_EINVAL (stage out of
+ * range, NULL plan), BSSN_ESTALE, BSSN_EHIP. */
+int batch_patches_stage(bssn_batch_plan* plan, int stage, void* stream);
 
 /* Same update without the persistent kernel or graph: one kernel launch per
  * patch and stage (the baseline the batched path is measured against). */

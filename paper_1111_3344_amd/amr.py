@@ -5,9 +5,14 @@ the fine solution restricted into the coarse one; fine-grid boundaries
 interpolated in space and time).
 
 This module only orders calls: every value is computed by the library
-(rk4_stage for the interior, bssn_amr_fill_ghosts for ghost points,
-bssn_amr_restrict for the coarse points under a fine patch).  Python keeps
-the times and rotates the time-level buffers.
+(the RK4 stages of a level's patches, bssn_amr_fill_ghosts for ghost
+points, bssn_amr_restrict for the coarse points under a fine patch).
+Python keeps the times and rotates the time-level buffers.
+
+A level's stages run either as one batched launch over all of its patches
+(batch_patches_stage of a plan per level and time-level rotation, the
+default) or as one rk4_stage per patch (batched=False); both run the same
+kernel arithmetic, so the two steppers agree bitwise.
 
 Per level L (spacing h_0 / 2^L, step dt_0 / 2^L) the stepper keeps three
 time levels of every patch: the current state and the two before it.  The
@@ -27,7 +32,7 @@ class BergerOliger:
     """hier: list of (level, grid); u0: device states (one per patch) at
     t = 0, taken over by the stepper; dt0: the level-0 step."""
 
-    def __init__(self, hier, params, dt0, u0):
+    def __init__(self, hier, params, dt0, u0, batched=True):
         import torch
         self.hier = list(hier)
         self.prm = params
@@ -43,6 +48,11 @@ class BergerOliger:
         self.acc = [torch.empty_like(t) for t in self.u]
         self.time = [0.0] * self.nlevel
         self.nsteps = [0] * self.nlevel
+        self.batched = batched
+        # batch plans per (level, rotation): the three time-level buffers
+        # of a patch take turns as u_n and u_{n+1}
+        self._plans = {}
+        self._rot = [0] * self.nlevel
 
     def _level(self, L, lst):
         return [t if lv == L else None for (lv, _), t in zip(self.hier, lst)]
@@ -77,8 +87,12 @@ class BergerOliger:
         idx = [p for p, (lv, _) in enumerate(self.hier) if lv == L]
         ins = (self.prev, self.a, self.b, self.a)
         outs = (self.a, self.b, self.a, self.u)
+        plan = self._plan(L, idx, dt) if self.batched else None
         for s in range(4):
             self._fill(L, self._level(L, ins[s]), T + STAGE_C[s] * dt)
+            if plan is not None:
+                B.batch_patches_stage(plan, s)
+                continue
             for p in idx:
                 g = self.hier[p][1]
                 B.rk4_stage(g, self.prm, s, dt, self.prev[p], ins[s][p],
@@ -93,6 +107,22 @@ class BergerOliger:
             self._advance(L + 1)
             self.plan.restrict(L + 1, self._level(L + 1, self.u),
                                self._level(L, self.u))
+
+    def _plan(self, L, idx, dt):
+        """The batch plan of level L for the current buffer rotation: u_n
+        in prev, u_{n+1} into u (stage inputs a, b as the plan's)."""
+        key = (L, self._rot[L])
+        self._rot[L] = (self._rot[L] + 1) % 3
+        plan = self._plans.get(key)
+        if plan is None:
+            grids = [self.hier[p][1] for p in idx]
+            plan = B.batch_patches_plan(
+                grids, self.prm, [self.prev[p] for p in idx],
+                [self.a[p] for p in idx], [self.b[p] for p in idx],
+                [self.acc[p] for p in idx], dt, autotune=0,
+                u_new=[self.u[p] for p in idx])
+            self._plans[key] = plan
+        return plan
 
     def step(self):
         """One level-0 step (2^L steps of every level L)."""

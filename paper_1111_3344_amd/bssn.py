@@ -137,6 +137,10 @@ def lib():
             L.batch_patches_plan.argtypes = [
                 ctypes.c_int, P(bssn_grid), p, P(vp), P(vp), P(vp), P(vp),
                 P(ctypes.c_double), ctypes.c_int, P(vp), vp]
+            L.batch_patches_plan_out.argtypes = [
+                ctypes.c_int, P(bssn_grid), p, P(vp), P(vp), P(vp), P(vp),
+                P(vp), P(ctypes.c_double), ctypes.c_int, P(vp), vp]
+            L.batch_patches_stage.argtypes = [vp, ctypes.c_int, vp]
             L.batch_patches.argtypes = [vp, ctypes.c_int, vp]
             L.batch_patches_unbatched.argtypes = [vp, ctypes.c_int, vp]
             L.batch_patches_describe.argtypes = [vp, ctypes.c_int,
@@ -391,11 +395,13 @@ class BatchPlan:
 
 
 def batch_patches_plan(grids, params, u, a, b, acc, dt, autotune=True,
-                       stream=None):
+                       stream=None, u_new=None):
+    """A batch plan; with u_new (one buffer per patch) its steps write
+    u_{n+1} there (batch_patches_plan_out) instead of into u."""
     n = len(grids)
     G = (bssn_grid * n)(*[c_grid(g) for g in grids])
     arrs = []
-    for bufs in (u, a, b, acc):
+    for bufs in (u, a, b, acc) + ((u_new,) if u_new is not None else ()):
         arrs.append((ctypes.c_void_p * n)(*[ptr(g, t) for g, t in
                                              zip(grids, bufs)]))
     # dt: one value for every patch, or one per patch
@@ -405,11 +411,22 @@ def batch_patches_plan(grids, params, u, a, b, acc, dt, autotune=True,
         raise ValueError(f"{len(dts)} time steps for {n} patches")
     dta = (ctypes.c_double * n)(*dts)
     h = ctypes.c_void_p()
-    _check(lib().batch_patches_plan(n, G, ctypes.byref(_params(params)),
-                                    arrs[0], arrs[1], arrs[2], arrs[3],
-                                    dta, int(autotune),
-                                    ctypes.byref(h), _stream(stream)))
-    return BatchPlan(h, (u, a, b, acc))
+    if u_new is None:
+        _check(lib().batch_patches_plan(n, G, ctypes.byref(_params(params)),
+                                        arrs[0], arrs[1], arrs[2], arrs[3],
+                                        dta, int(autotune),
+                                        ctypes.byref(h), _stream(stream)))
+        return BatchPlan(h, (u, a, b, acc))
+    _check(lib().batch_patches_plan_out(n, G, ctypes.byref(_params(params)),
+                                        arrs[0], arrs[4], arrs[1], arrs[2],
+                                        arrs[3], dta, int(autotune),
+                                        ctypes.byref(h), _stream(stream)))
+    return BatchPlan(h, (u, a, b, acc, u_new))
+
+
+def batch_patches_stage(plan, stage, stream=None):
+    _check(lib().batch_patches_stage(plan.handle, int(stage),
+                                     _stream(stream)))
 
 
 def batch_patches(plan, nsteps, stream=None):

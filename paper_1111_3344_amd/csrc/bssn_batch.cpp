@@ -275,8 +275,14 @@ struct bssn_batch_plan {
   hipStream_t cs = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipGraph_t sgraph[4] = {};          // one stage each (batch_patches_stage)
+  hipGraphExec_t sexec[4] = {};
 
   ~bssn_batch_plan() {
+    for (int s = 0; s < 4; ++s) {
+      if (sexec[s]) (void)hipGraphExecDestroy(sexec[s]);
+      if (sgraph[s]) (void)hipGraphDestroy(sgraph[s]);
+    }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cs) (void)hipStreamDestroy(cs);
@@ -306,11 +312,11 @@ int check_fresh(const bssn_batch_plan* plan) {
     if (e != hipSuccess) {
       (void)hipGetLastError();  // do not leave the query's error behind
       return fail(BSSN_ESTALE, "batch plan buffer %zu (patch %zu) is no "
-                  "longer allocated", i % 4, i / 4);
+                  "longer allocated", i % 5, i / 5);
     }
     if (r.base != plan->ranges[i].base || r.size != plan->ranges[i].size)
       return fail(BSSN_ESTALE, "batch plan buffer %zu (patch %zu) lies in a "
-                  "different allocation than at plan time", i % 4, i / 4);
+                  "different allocation than at plan time", i % 5, i / 5);
   }
   return BSSN_OK;
 }
@@ -406,7 +412,10 @@ int record_graph(bssn_batch_plan* P, int autotune, hipStream_t st) {
     P->mode = P->mode_ms[kPerPatch] < P->mode_ms[kPersistent] ? kPerPatch
                                                               : kPersistent;
   }
-  return capture(P, P->mode, 0, 4, &P->graph, &P->exec);
+  int rc = capture(P, P->mode, 0, 4, &P->graph, &P->exec);
+  for (int s = 0; s < 4 && rc == BSSN_OK; ++s)
+    rc = capture(P, P->mode, s, s + 1, &P->sgraph[s], &P->sexec[s]);
+  return rc;
 }
 
 // Milliseconds of one batched stage-0 launch of variant v over pids (best
@@ -557,11 +566,12 @@ int plan_build(bssn_batch_plan* P, int autotune, hipStream_t st) {
 
 extern "C" {
 
-int batch_patches_plan(int npatch, const bssn_grid* grids,
-                       const bssn_params* params, double* const* u,
-                       double* const* a, double* const* b,
-                       double* const* acc, const double* dt, int autotune,
-                       bssn_batch_plan** plan, void* stream) {
+namespace {
+// batch_patches_plan with stage 3 writing u_new[p] (NULL: u[p] itself).
+int plan_create(int npatch, const bssn_grid* grids, const bssn_params* params,
+                double* const* u, double* const* u_new, double* const* a,
+                double* const* b, double* const* acc, const double* dt,
+                int autotune, bssn_batch_plan** plan, void* stream) {
   if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
   *plan = nullptr;
   int rc = check_params(params);
@@ -598,6 +608,12 @@ int batch_patches_plan(int npatch, const bssn_grid* grids,
         if (q[i] == q[j])
           return fail(BSSN_EINVAL, "patch %d: buffers %d and %d alias", p, j, i);
     }
+    if (u_new) {
+      if (!u_new[p]) return fail(BSSN_EINVAL, "patch %d: u_new is NULL", p);
+      for (int j = 1; j < 4; ++j)
+        if (u_new[p] == q[j])
+          return fail(BSSN_EINVAL, "patch %d: u_new aliases buffer %d", p, j);
+    }
   }
   bssn_batch_plan* P = new (std::nothrow) bssn_batch_plan();
   if (!P) return fail(BSSN_ENOMEM, "batch plan");
@@ -619,14 +635,15 @@ int batch_patches_plan(int npatch, const bssn_grid* grids,
     base.u_n = u[p];
     base.acc = acc[p];
     const double* us[4] = {u[p], a[p], b[p], a[p]};
-    double* out[4] = {a[p], b[p], a[p], u[p]};
+    double* out[4] = {a[p], b[p], a[p], u_new ? u_new[p] : u[p]};
     for (int s = 0; s < 4; ++s) {
       Patch q = base;
       q.u_s = us[s];
       q.out = out[s];
       P->hp[s][p] = q;
     }
-    const void* bufs[4] = {u[p], a[p], b[p], acc[p]};
+    const void* bufs[5] = {u[p], a[p], b[p], acc[p],
+                           u_new ? u_new[p] : u[p]};
     for (const void* ptr : bufs) {
       AddrRange r{};
       e = hipMemGetAddressRange(&r.base, &r.size, (hipDeviceptr_t)ptr);
@@ -655,6 +672,41 @@ int batch_patches_plan(int npatch, const bssn_grid* grids,
     return rc;
   }
   *plan = P;
+  return BSSN_OK;
+}
+}  // namespace
+
+int batch_patches_plan(int npatch, const bssn_grid* grids,
+                       const bssn_params* params, double* const* u,
+                       double* const* a, double* const* b,
+                       double* const* acc, const double* dt, int autotune,
+                       bssn_batch_plan** plan, void* stream) {
+  return plan_create(npatch, grids, params, u, nullptr, a, b, acc, dt,
+                     autotune, plan, stream);
+}
+
+int batch_patches_plan_out(int npatch, const bssn_grid* grids,
+                           const bssn_params* params, double* const* u,
+                           double* const* u_new, double* const* a,
+                           double* const* b, double* const* acc,
+                           const double* dt, int autotune,
+                           bssn_batch_plan** plan, void* stream) {
+  if (!u_new) {
+    if (plan) *plan = nullptr;
+    return fail(BSSN_EINVAL, "u_new is NULL");
+  }
+  return plan_create(npatch, grids, params, u, u_new, a, b, acc, dt,
+                     autotune, plan, stream);
+}
+
+int batch_patches_stage(bssn_batch_plan* plan, int stage, void* stream) {
+  if (!plan) return fail(BSSN_EINVAL, "plan is NULL");
+  if (stage < 0 || stage > 3)
+    return fail(BSSN_EINVAL, "stage = %d outside 0..3", stage);
+  int rc = check_fresh(plan);
+  if (rc) return rc;
+  hipError_t e = hipGraphLaunch(plan->sexec[stage], (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch (stage)");
   return BSSN_OK;
 }
 

@@ -273,6 +273,29 @@ def test_rk4_stage_radiative_validation():
     assert "outermost interior layer" in B.bssn_last_error()
 
 
+def test_batch_stage_and_plan_out_validation():
+    L = B.lib()
+    g = I.cell_centred(8, -1, 1, 3)
+    G = (B.bssn_grid * 1)(B.c_grid(g))
+    prm = B.Params().c()
+    arr = lambda v: (ctypes.c_void_p * 1)(v)
+    dt = (ctypes.c_double * 1)(0.1)
+    h = ctypes.c_void_p()
+    # u_new aliasing a / acc, or NULL, is rejected before any allocation
+    for un in (1 << 20, 3 << 20, None):
+        rc = L.batch_patches_plan_out(1, G, ctypes.byref(prm), arr(1 << 20),
+                                      None if un is None else arr(un),
+                                      arr(2 << 20), arr(4 << 20),
+                                      arr(3 << 20), dt, 0, ctypes.byref(h),
+                                      None)
+        if un == 1 << 20:
+            # u_new == u is allowed: fails later, on the fake pointers
+            assert rc != B.BSSN_OK
+        else:
+            assert rc == B.BSSN_EINVAL
+    assert L.batch_patches_stage(None, 0, None) == B.BSSN_EINVAL
+
+
 def test_psi4_validation():
     L = B.lib()
     g = I.cell_centred(8, -1, 1, 3)
