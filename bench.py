@@ -296,7 +296,8 @@ def time_amr_step(B, torch, g, wl, order, steps=3, precision=None,
         drv.step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    level_steps = sum(2 ** L for L, _ in hier)
+    levels = sorted({L for L, _ in hier})
+    level_steps = sum(2 ** L for L in levels)
     upd = sum(gr.npoints * 2 ** L for L, gr in hier)
     ok = all(bool(torch.isfinite(x).all()) for x in drv.u)
     del drv, u0
