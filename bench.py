@@ -155,9 +155,10 @@ def time_radiative(B, torch, g, u_host, prm, reps=20, warmup=2):
 
 def time_radiative_step(B, torch, g, u_host, prm, steps=10, warmup=2):
     """Whole RK4 steps with the radiative boundary evolved
-    (rk4_stage_radiative: shell right-hand side, fused interior stage,
-    boundary stage update per stage) against the same steps with static
-    ghosts (rk4_stage), HIP events on the launch stream."""
+    (rk4_stage_radiative: the fused interior stage, which also stores the
+    right-hand side of the outermost interior layer, then the boundary
+    stage update) against the same steps with static ghosts (rk4_stage),
+    HIP events on the launch stream."""
     du = torch.from_numpy(u_host).to("cuda")
     a, b, acc, k = (torch.zeros_like(du) for _ in range(4))
     stream = torch.cuda.current_stream()
@@ -184,8 +185,9 @@ def time_radiative_step(B, torch, g, u_host, prm, steps=10, warmup=2):
     finite = bool(torch.isfinite(du).all().item())
     del du, a, b, acc, k
     torch.cuda.empty_cache()
-    return {"kernels": "k_shell_rhs, k_stage_lds, k_radiative_stage per "
-                       "stage",
+    return {"kernels": "k_stage_lds (also storing the right-hand side of "
+                       "the outermost interior layer), k_radiative_stage "
+                       "per stage",
             "ms_per_step_radiative": round(res["radiative"], 4),
             "ms_per_step_static": round(res["static"], 4),
             "overhead": round(res["radiative"] / res["static"] - 1.0, 4),

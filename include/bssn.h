@@ -319,15 +319,17 @@ int bssn_radiative_rhs(const bssn_grid* grid, const double* x0,
  *   s = 2: acc = acc + dt/3 k,  u_out = u_n + dt k
  *   s = 3:                      u_out = acc + dt/6 k
  * The boundary is carried outward from the interior right-hand side at the
- * outermost layer of interior points, which this call evaluates in FP64
- * (in either precision) into k.
+ * outermost layer of interior points, which the interior stage leaves in k
+ * (as it computes it: FP64, or in mixed precision the arithmetic of the
+ * point's tile).
  *   stage, dt, u_n, u_s, acc, u_out  as rk4_stage (same aliasing rules)
  *   k   device work buffer in the state layout (25 slots), aliasing no other
  *       buffer; on return its outermost interior layer holds the interior
  *       right-hand side there, everything else in it is untouched
  * Needs a static grid whose coordinate origin is neither a ghost point nor
- * on the outermost interior layer (r = 0 there).  Three launches on
- * `stream`.  Errors: BSSN_EINVAL, BSSN_EUNSUPPORTED, BSSN_EHIP. */
+ * on the outermost interior layer (r = 0 there).  The launches of the
+ * interior stage and one more on `stream`.  Errors: BSSN_EINVAL,
+ * BSSN_EUNSUPPORTED, BSSN_EHIP. */
 int rk4_stage_radiative(const bssn_grid* grid, const bssn_params* params,
                         int stage, double dt, const double* x0,
                         const double* v0, int power, const double* u_n,

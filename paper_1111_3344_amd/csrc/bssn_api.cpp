@@ -426,25 +426,20 @@ int rk4_stage_radiative(const bssn_grid* grid, const bssn_params* params,
   if ((rc = radiative_args(grid, x0, v0, power, u_s, k, A))) return rc;
   const hipStream_t st = (hipStream_t)stream;
   const Gauge G = make_gauge(params);
-  // 1. the interior right-hand side at the radiative boundary's roots
-  Patch S = make_patch(grid);
-  S.u_s = u_s;
-  S.u_n = u_s;
-  S.acc = nullptr;
-  S.out = k;
-  S.dt = 0.0;
-  hipError_t e = launch_shell_rhs(S, G, params->fd_order, st);
-  if (e != hipSuccess) return hip_fail(e, "rk4_stage_radiative shell launch");
-  // 2. the fused stage at the interior points
+  // 1. the fused stage at the interior points; it also leaves the
+  //    right-hand side of the outermost interior layer (the radiative
+  //    boundary's roots) in k
   Patch P = make_patch(grid);
   P.u_s = u_s;
   P.u_n = u_n;
   P.acc = acc;
   P.out = u_out;
   P.dt = dt;
-  e = launch_stage(P, G, params->fd_order, 0, stage, params->precision, st);
+  P.kout = k;
+  hipError_t e =
+      launch_stage(P, G, params->fd_order, 0, stage, params->precision, st);
   if (e != hipSuccess) return hip_fail(e, "rk4_stage_radiative launch");
-  // 3. the boundary points: radiative right-hand side and stage update
+  // 2. the boundary points: radiative right-hand side and stage update
   RadStage R{u_n, acc, u_out, dt, stage};
   e = launch_radiative_stage(A, R, st);
   if (e != hipSuccess)

@@ -7,7 +7,11 @@
 namespace bssn {
 
 // One RK4 stage (or the bare RHS for stage ST_RHS) on one patch.
-// precision 0: FP64; 1: FP32 tiles + FP64 tiles (two launches).
+// precision 0: FP64; 1: FP32 tiles + FP64 tiles (two launches).  With
+// P.kout set, the right-hand side at the outermost layer of interior points
+// (the radiative boundary's roots) also goes to P.kout: stored by the LDS
+// kernels from their own tiles, or by the shell kernel (FP64) before a
+// direct-kernel stage.
 // Kernel choice: PATH_AUTO uses the LDS-pipelined persistent kernel for
 // static grids whose layout allows 16-byte granules, the direct-load kernel
 // otherwise; PATH_DIRECT forces the direct-load kernel.
@@ -27,16 +31,6 @@ inline hipError_t launch_stage(const Patch& P, const Gauge& G, int order,
   return order == 8
              ? launch_stage_o8(P, G, periodic, stage, precision, path, nwg, st)
              : launch_stage_o4(P, G, periodic, stage, precision, path, nwg, st);
-}
-
-// FP64 right-hand side (P.out, state layout) at the outermost layer of
-// interior points of a static patch (the radiative boundary's roots).
-hipError_t launch_shell_rhs_o4(const Patch& P, const Gauge& G, hipStream_t st);
-hipError_t launch_shell_rhs_o8(const Patch& P, const Gauge& G, hipStream_t st);
-inline hipError_t launch_shell_rhs(const Patch& P, const Gauge& G, int order,
-                                   hipStream_t st) {
-  return order == 8 ? launch_shell_rhs_o8(P, G, st)
-                    : launch_shell_rhs_o4(P, G, st);
 }
 
 // One static patch with an explicit kernel variant (VAR_*); nwg bounds the

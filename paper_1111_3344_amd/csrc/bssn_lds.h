@@ -659,18 +659,28 @@ __device__ __forceinline__ double tile_lapse_min(const double* sc,
 }
 
 // The point function and epilogue of one thread's point in arithmetic T.
-template <int ORDER, typename T, bool EARLY, class LD>
+// KSH: a point on the outermost interior layer (shell) also stores its
+// right-hand side to P.kout (the radiative boundary's roots); the stores
+// follow the epilogue's.
+template <int ORDER, typename T, bool EARLY, bool KSH, class LD>
 __device__ __forceinline__ void tile_point(const LD& ld, const Patch& P,
                                            const Gauge& G, int stage,
                                            double xc, double yc, double zc,
                                            uint32_t vc, int32_t nbytes,
-                                           bool active) {
+                                           bool active, bool shell) {
   T r[NSLOT];
   point_rhs<ORDER, T>(ld, P, xc, yc, zc, G, r);
   if (EARLY) {
     if (active) epilogue_store<T>(P, stage, r, vc, nbytes, ld.un, ld.ac);
   } else {
     epilogue_all<T>(P, stage, r, ld.vc_epi, nbytes, active);
+  }
+  if constexpr (KSH) {
+    if (active && shell) {
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s)
+        bstore_nt(slot_rsrc(P.kout, P.sf, s, nbytes), vc, double(r[s]));
+    }
   }
 }
 
@@ -679,7 +689,7 @@ __device__ __forceinline__ void tile_point(const LD& ld, const Patch& P,
 // On return every DMA of this call has landed; the caller places a barrier
 // before the ring is filled again.
 template <int ORDER, int TP, bool TRIM, class Geo = TileGeo<ORDER>,
-          class WK = Walk>
+          class WK = Walk, bool KSH = false>
 __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
                                           const int stage, const WK& Wk,
                                           double* ring, double* sc,
@@ -714,6 +724,8 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     Wk.origin(k, x0, y0, z0);
     const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
     const bool active = x < P.n[0] && y < P.n[1] && z < P.n[2];
+    const bool shell = KSH && (x == 0 || y == 0 || z == 0 || x == P.n[0] - 1 ||
+                               y == P.n[1] - 1 || z == P.n[2] - 1);
     const int g = P.ghost;
     // early epilogue loads where the registers allow (order 4, FP64);
     // corner-based tap addressing for the FP32 and order-8 kernels
@@ -753,8 +765,8 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     const double zc = P.origin[2] + z * P.h[2];
     bool computed = true;
     if constexpr (TP == TP_F64) {
-      tile_point<ORDER, double, early>(ld, P, G, stage, xc, yc, zc, vc,
-                                       nbytes, active);
+      tile_point<ORDER, double, early, KSH>(ld, P, G, stage, xc, yc, zc, vc,
+                                            nbytes, active, shell);
     } else {
       if (tile_lapse_min(sc, P, x, y, z0, lane) < G.alpha_thr) {
         // left to the FP64 pass: keep the pipeline going (waits, barriers,
@@ -763,8 +775,8 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
         for (int p = 1; p < NSLOT; ++p) ld.phase(p);
         computed = false;
       } else {
-        tile_point<ORDER, float, early>(ld, P, G, stage, xc, yc, zc, vc,
-                                        nbytes, active);
+        tile_point<ORDER, float, early, KSH>(ld, P, G, stage, xc, yc, zc, vc,
+                                             nbytes, active, shell);
       }
     }
     prev_loads =
@@ -772,6 +784,11 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     prev_stores = computed && __builtin_amdgcn_ballot_w64(active) != 0
                       ? epilogue_stores(stage)
                       : 0;
+    // the shell stores of this wave, if any lane made them (a wave whose
+    // lanes all skip them may still issue them with no lane enabled, which
+    // only makes the next waits longer than needed)
+    if (KSH && computed && __builtin_amdgcn_ballot_w64(active && shell) != 0)
+      prev_stores += NSLOT;
     // next tile: its box base becomes current, prepare the one after
     tbA = tbB;
     if (k + 2 < ntile_mine) {
@@ -809,8 +826,9 @@ __device__ __forceinline__ Walk walk_of(const TileMap& M, int nwg) {
   return w;
 }
 
-// One patch, FP64: workgroup b takes the tiles of walk_of(b).
-template <int ORDER>
+// One patch, FP64: workgroup b takes the tiles of walk_of(b).  KSH: also
+// the right-hand side at the outermost interior layer into P.kout.
+template <int ORDER, bool KSH = false>
 __global__ void __launch_bounds__(256)
     k_stage_lds(const Patch P, const Gauge G, const int stage,
                 const TileMap M) {
@@ -820,13 +838,13 @@ __global__ void __launch_bounds__(256)
   __shared__ __attribute__((aligned(16))) double mixs[mix_doubles<Geo>()];
   // trimmed DMA: granules no stencil reads are not fetched (3-4% faster
   // at order 4 too since the DMA offsets became lane constants)
-  lds_tiles<ORDER, TP_F64, true>(P, G, stage, walk_of(M, gridDim.x),
-                                       ring, sc, mixs);
+  lds_tiles<ORDER, TP_F64, true, TileGeo<ORDER>, Walk, KSH>(
+      P, G, stage, walk_of(M, gridDim.x), ring, sc, mixs);
 }
 
 // One patch, mixed precision, first launch: the FP32 tiles.  At order 4
 // two workgroups share a CU (GeoF32 ring, at most 256 registers per lane).
-template <int ORDER>
+template <int ORDER, bool KSH = false>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(ORDER == 4 ? 2 : 1,
                                        ORDER == 4 ? 2 : 1)))
@@ -836,8 +854,8 @@ __global__ void __launch_bounds__(256)
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
   __shared__ __attribute__((aligned(16))) double mixs[mix_doubles<Geo>()];
-  lds_tiles<ORDER, TP_F32, true, Geo>(P, G, stage, walk_of(M, gridDim.x),
-                                      ring, sc, mixs);
+  lds_tiles<ORDER, TP_F32, true, Geo, Walk, KSH>(
+      P, G, stage, walk_of(M, gridDim.x), ring, sc, mixs);
 }
 
 // Tiles named by an LDS list of tile numbers (TileMap numbering).
@@ -918,7 +936,7 @@ __device__ __forceinline__ int compact_flags(bool f, int val, int* list,
 // around a puncture (neighbours in the numbering) land on many workgroups.
 // The tiles whose minimum lapse is below the threshold run through the FP64
 // pipeline.
-template <int ORDER>
+template <int ORDER, bool KSH = false>
 __global__ void __launch_bounds__(256)
     k_stage_lds_f64tiles(const Patch P, const Gauge G, const int stage,
                          const TileMap M, const int perm) {
@@ -945,7 +963,8 @@ __global__ void __launch_bounds__(256)
     const int n = compact_flags(f, t, list, wcnt);
     if (n > 0) {
       const ListWalk w{(const lds_int*)list, n, M.ntx, M.ntz};
-      lds_tiles<ORDER, TP_F64, true>(P, G, stage, w, ring, sc, mixs);
+      lds_tiles<ORDER, TP_F64, true, TileGeo<ORDER>, ListWalk, KSH>(
+          P, G, stage, w, ring, sc, mixs);
     }
     __syncthreads();  // ring, sc, list and wcnt are reused
   }
@@ -1107,28 +1126,38 @@ namespace bssn {
 // precision 0: one FP64 launch.  Mixed: the FP32 tiles (two workgroups per
 // CU at order 4), then the FP64 tiles; both launches take the same per-tile
 // decision from the stage input, so each tile is written exactly once.
-template <int ORDER>
-hipError_t launch_stage_lds(const Patch& P, const Gauge& G, int stage,
-                            int precision, int nwg_max, hipStream_t st) {
+template <int ORDER, bool KSH>
+hipError_t launch_stage_lds_k(const Patch& P, const Gauge& G, int stage,
+                              int precision, int nwg_max, hipStream_t st) {
   TileMap M = lds_tile_map<ORDER>(P);
   const int nwg = M.ntiles < nwg_max ? M.ntiles : nwg_max;
   if (precision == 0) {
     choose_blocks<ORDER>(M, nwg);
-    hipLaunchKernelGGL((k_stage_lds<ORDER>), dim3(nwg), dim3(256), 0, st, P,
-                       G, stage, M);
+    hipLaunchKernelGGL((k_stage_lds<ORDER, KSH>), dim3(nwg), dim3(256), 0, st,
+                       P, G, stage, M);
     return hipGetLastError();
   }
   const int per_cu = ORDER == 4 ? 2 : 1;
   const int nwg32 = M.ntiles < per_cu * nwg_max ? M.ntiles : per_cu * nwg_max;
   TileMap M32 = M;
   choose_blocks<ORDER>(M32, nwg32);
-  hipLaunchKernelGGL((k_stage_lds_f32<ORDER>), dim3(nwg32), dim3(256), 0, st,
-                     P, G, stage, M32);
+  hipLaunchKernelGGL((k_stage_lds_f32<ORDER, KSH>), dim3(nwg32), dim3(256), 0,
+                     st, P, G, stage, M32);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_stage_lds_f64tiles<ORDER>), dim3(nwg), dim3(256), 0,
-                     st, P, G, stage, M, int(tile_perm(M.ntiles)));
+  hipLaunchKernelGGL((k_stage_lds_f64tiles<ORDER, KSH>), dim3(nwg), dim3(256),
+                     0, st, P, G, stage, M, int(tile_perm(M.ntiles)));
   return hipGetLastError();
+}
+// P.kout set: the kernels that also store the right-hand side at the
+// outermost interior layer.
+template <int ORDER>
+hipError_t launch_stage_lds(const Patch& P, const Gauge& G, int stage,
+                            int precision, int nwg_max, hipStream_t st) {
+  return P.kout ? launch_stage_lds_k<ORDER, true>(P, G, stage, precision,
+                                                  nwg_max, st)
+                : launch_stage_lds_k<ORDER, false>(P, G, stage, precision,
+                                                   nwg_max, st);
 }
 
 // Explicit-variant launch of one static patch, and batched launches.

@@ -10,15 +10,18 @@ hipError_t launch_stage_o4(const Patch& P, const Gauge& G, int periodic,
                            hipStream_t st) {
   const bool lds = !periodic && path != PATH_DIRECT && lds_path_ok<4>(P);
   if (lds) return launch_stage_lds<4>(P, G, stage, precision, nwg, st);
+  if (P.kout) {
+    // the direct kernels do not store the shell's right-hand side: the
+    // shell kernel does, before the stage
+    Patch S = P;
+    S.out = P.kout;
+    const hipError_t e = launch_shell_rhs_t<4>(S, G, st);
+    if (e != hipSuccess) return e;
+  }
   return periodic
              ? launch_stage_variant<4, true>(P, G, stage, precision, 0, st)
              : launch_stage_variant<4, false>(P, G, stage, precision, 0,
                                                    st);
-}
-
-hipError_t launch_shell_rhs_o4(const Patch& P, const Gauge& G,
-                               hipStream_t st) {
-  return launch_shell_rhs_t<4>(P, G, st);
 }
 
 hipError_t launch_patch_o4(const Patch& P, const Gauge& G, int stage,
