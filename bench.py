@@ -16,7 +16,9 @@ the same run), `cpu_baseline` the FP64 oracle on the host cores (model,
 thread count, one-thread rate).  `workloads` adds the 256^3 and 128^3
 grids (FP64 and mixed; on 128^3 also the constraint norms after 100 RK4
 steps) and the 256 uneven patches (batched against one launch per patch);
-`extras` times the steps around the path on the 128^3 grid.
+`extras` times the steps around the path on the 128^3 grid; `accuracy`
+runs the 384^3 (50 steps) and 256^3 (200 steps) workloads in FP64 and in
+mixed precision and compares fields and constraint norms.
 
 Profiling support (the summaries under profiles/ are made this way):
     rocprofv3 --kernel-trace --stats --output-format csv -d D -o run \
@@ -582,11 +584,14 @@ def summarize_profile(dirs, order=4):
     import collections
     import re
     out = []
-    kernels = (("", re.compile(r"k_stage_lds<\s*%d\s*>\(" % order)),
-               ("mixed_f32_", re.compile(r"k_stage_lds_f32<\s*%d\s*>\(" %
-                                         order)),
+    # the production instantiations (the second template argument, false,
+    # is the radiative-boundary variant's switch)
+    tail = r"\s*(,\s*false\s*)?>\("
+    kernels = (("", re.compile(r"k_stage_lds<\s*%d" % order + tail)),
+               ("mixed_f32_", re.compile(r"k_stage_lds_f32<\s*%d" % order +
+                                         tail)),
                ("mixed_f64pass_", re.compile(
-                   r"k_stage_lds_f64tiles<\s*%d\s*>\(" % order)))
+                   r"k_stage_lds_f64tiles<\s*%d" % order + tail)))
 
     def tag(name):
         for t, rx in kernels:
@@ -1100,6 +1105,10 @@ def main():
                             **batched(B, torch, args.steps, args.warmup)}
         out["workloads"] = wk
         out["extras"] = extras(B, torch, "bl1-128", 4)
+        # mixed precision against FP64 over each workload's full run:
+        # field error and constraint norms (the mixed form's bound)
+        out["accuracy"] = {name: accuracy(B, torch, name)
+                           for name in ("bl2-384-o8", "bl2-256")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -435,9 +435,8 @@ int rk4_stage_radiative(const bssn_grid* grid, const bssn_params* params,
   P.acc = acc;
   P.out = u_out;
   P.dt = dt;
-  P.kout = k;
-  hipError_t e =
-      launch_stage(P, G, params->fd_order, 0, stage, params->precision, st);
+  hipError_t e = launch_stage(P, G, params->fd_order, 0, stage,
+                              params->precision, st, k);
   if (e != hipSuccess) return hip_fail(e, "rk4_stage_radiative launch");
   // 2. the boundary points: radiative right-hand side and stage update
   RadStage R{u_n, acc, u_out, dt, stage};

@@ -37,10 +37,6 @@ struct Patch {
   // uniform inverse spacings, computed on the host so they stay in SGPRs:
   // 1/h_a, 1/h_a^2, and 1/(h_x h_y), 1/(h_x h_z), 1/(h_y h_z)
   double ih[3], ih2[3], ihm[3];
-  // optional: the stage's right-hand side at the outermost layer of
-  // interior points (the radiative boundary's roots), state layout; null
-  // for every other use
-  double* kout;
 };
 
 struct Gauge {

@@ -8,29 +8,30 @@ namespace bssn {
 
 // One RK4 stage (or the bare RHS for stage ST_RHS) on one patch.
 // precision 0: FP64; 1: FP32 tiles + FP64 tiles (two launches).  With
-// P.kout set, the right-hand side at the outermost layer of interior points
-// (the radiative boundary's roots) also goes to P.kout: stored by the LDS
-// kernels from their own tiles, or by the shell kernel (FP64) before a
-// direct-kernel stage.
+// kout set, the right-hand side at the outermost layer of interior points
+// (the radiative boundary's roots) also goes to kout (state layout):
+// stored by the LDS kernels from their own tiles, or by the shell kernel
+// (FP64) before a direct-kernel stage.
 // Kernel choice: PATH_AUTO uses the LDS-pipelined persistent kernel for
 // static grids whose layout allows 16-byte granules, the direct-load kernel
 // otherwise; PATH_DIRECT forces the direct-load kernel.
 enum : int { PATH_AUTO = 0, PATH_DIRECT = 1 };
 hipError_t launch_stage_o4(const Patch& P, const Gauge& G, int periodic,
                            int stage, int precision, int path, int nwg,
-                           hipStream_t st);
+                           hipStream_t st, double* kout = nullptr);
 hipError_t launch_stage_o8(const Patch& P, const Gauge& G, int periodic,
                            int stage, int precision, int path, int nwg,
-                           hipStream_t st);
+                           hipStream_t st, double* kout = nullptr);
 int stage_path();          // current PATH_* (bssn_set_path)
 int persistent_groups();   // workgroups of a persistent launch (CU count)
 inline hipError_t launch_stage(const Patch& P, const Gauge& G, int order,
                                int periodic, int stage, int precision,
-                               hipStream_t st) {
+                               hipStream_t st, double* kout = nullptr) {
   const int path = stage_path(), nwg = persistent_groups();
-  return order == 8
-             ? launch_stage_o8(P, G, periodic, stage, precision, path, nwg, st)
-             : launch_stage_o4(P, G, periodic, stage, precision, path, nwg, st);
+  return order == 8 ? launch_stage_o8(P, G, periodic, stage, precision, path,
+                                      nwg, st, kout)
+                    : launch_stage_o4(P, G, periodic, stage, precision, path,
+                                      nwg, st, kout);
 }
 
 // One static patch with an explicit kernel variant (VAR_*); nwg bounds the

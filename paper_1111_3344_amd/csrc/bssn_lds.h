@@ -660,14 +660,15 @@ __device__ __forceinline__ double tile_lapse_min(const double* sc,
 
 // The point function and epilogue of one thread's point in arithmetic T.
 // KSH: a point on the outermost interior layer (shell) also stores its
-// right-hand side to P.kout (the radiative boundary's roots); the stores
-// follow the epilogue's.
+// right-hand side to kout (the radiative boundary's roots, state layout);
+// the stores follow the epilogue's.
 template <int ORDER, typename T, bool EARLY, bool KSH, class LD>
 __device__ __forceinline__ void tile_point(const LD& ld, const Patch& P,
                                            const Gauge& G, int stage,
                                            double xc, double yc, double zc,
                                            uint32_t vc, int32_t nbytes,
-                                           bool active, bool shell) {
+                                           bool active, bool shell,
+                                           double* kout) {
   T r[NSLOT];
   point_rhs<ORDER, T>(ld, P, xc, yc, zc, G, r);
   if (EARLY) {
@@ -679,7 +680,7 @@ __device__ __forceinline__ void tile_point(const LD& ld, const Patch& P,
     if (active && shell) {
 #pragma unroll
       for (int s = 0; s < NSLOT; ++s)
-        bstore_nt(slot_rsrc(P.kout, P.sf, s, nbytes), vc, double(r[s]));
+        bstore_nt(slot_rsrc(kout, P.sf, s, nbytes), vc, double(r[s]));
     }
   }
 }
@@ -693,7 +694,8 @@ template <int ORDER, int TP, bool TRIM, class Geo = TileGeo<ORDER>,
 __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
                                           const int stage, const WK& Wk,
                                           double* ring, double* sc,
-                                          double* mixs) {
+                                          double* mixs,
+                                          double* kout = nullptr) {
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
@@ -766,7 +768,7 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     bool computed = true;
     if constexpr (TP == TP_F64) {
       tile_point<ORDER, double, early, KSH>(ld, P, G, stage, xc, yc, zc, vc,
-                                            nbytes, active, shell);
+                                            nbytes, active, shell, kout);
     } else {
       if (tile_lapse_min(sc, P, x, y, z0, lane) < G.alpha_thr) {
         // left to the FP64 pass: keep the pipeline going (waits, barriers,
@@ -776,7 +778,7 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
         computed = false;
       } else {
         tile_point<ORDER, float, early, KSH>(ld, P, G, stage, xc, yc, zc, vc,
-                                             nbytes, active, shell);
+                                             nbytes, active, shell, kout);
       }
     }
     prev_loads =
@@ -827,11 +829,11 @@ __device__ __forceinline__ Walk walk_of(const TileMap& M, int nwg) {
 }
 
 // One patch, FP64: workgroup b takes the tiles of walk_of(b).  KSH: also
-// the right-hand side at the outermost interior layer into P.kout.
+// the right-hand side at the outermost interior layer into kout.
 template <int ORDER, bool KSH = false>
 __global__ void __launch_bounds__(256)
     k_stage_lds(const Patch P, const Gauge G, const int stage,
-                const TileMap M) {
+                const TileMap M, double* const kout) {
   using Geo = TileGeo<ORDER>;
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
@@ -839,7 +841,7 @@ __global__ void __launch_bounds__(256)
   // trimmed DMA: granules no stencil reads are not fetched (3-4% faster
   // at order 4 too since the DMA offsets became lane constants)
   lds_tiles<ORDER, TP_F64, true, TileGeo<ORDER>, Walk, KSH>(
-      P, G, stage, walk_of(M, gridDim.x), ring, sc, mixs);
+      P, G, stage, walk_of(M, gridDim.x), ring, sc, mixs, kout);
 }
 
 // One patch, mixed precision, first launch: the FP32 tiles.  At order 4
@@ -849,13 +851,13 @@ __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(ORDER == 4 ? 2 : 1,
                                        ORDER == 4 ? 2 : 1)))
     k_stage_lds_f32(const Patch P, const Gauge G, const int stage,
-                    const TileMap M) {
+                    const TileMap M, double* const kout) {
   using Geo = GeoF32<ORDER>;
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
   __shared__ __attribute__((aligned(16))) double mixs[mix_doubles<Geo>()];
   lds_tiles<ORDER, TP_F32, true, Geo, Walk, KSH>(
-      P, G, stage, walk_of(M, gridDim.x), ring, sc, mixs);
+      P, G, stage, walk_of(M, gridDim.x), ring, sc, mixs, kout);
 }
 
 // Tiles named by an LDS list of tile numbers (TileMap numbering).
@@ -939,7 +941,8 @@ __device__ __forceinline__ int compact_flags(bool f, int val, int* list,
 template <int ORDER, bool KSH = false>
 __global__ void __launch_bounds__(256)
     k_stage_lds_f64tiles(const Patch P, const Gauge G, const int stage,
-                         const TileMap M, const int perm) {
+                         const TileMap M, const int perm,
+                         double* const kout) {
   using Geo = TileGeo<ORDER>;
   __shared__ __attribute__((aligned(16))) double ring[Geo::NBUF * Geo::BUFD];
   __shared__ __attribute__((aligned(16))) double sc[kNCentre * 256];
@@ -964,7 +967,7 @@ __global__ void __launch_bounds__(256)
     if (n > 0) {
       const ListWalk w{(const lds_int*)list, n, M.ntx, M.ntz};
       lds_tiles<ORDER, TP_F64, true, TileGeo<ORDER>, ListWalk, KSH>(
-          P, G, stage, w, ring, sc, mixs);
+          P, G, stage, w, ring, sc, mixs, kout);
     }
     __syncthreads();  // ring, sc, list and wcnt are reused
   }
@@ -1128,13 +1131,14 @@ namespace bssn {
 // decision from the stage input, so each tile is written exactly once.
 template <int ORDER, bool KSH>
 hipError_t launch_stage_lds_k(const Patch& P, const Gauge& G, int stage,
-                              int precision, int nwg_max, hipStream_t st) {
+                              int precision, int nwg_max, hipStream_t st,
+                              double* kout) {
   TileMap M = lds_tile_map<ORDER>(P);
   const int nwg = M.ntiles < nwg_max ? M.ntiles : nwg_max;
   if (precision == 0) {
     choose_blocks<ORDER>(M, nwg);
     hipLaunchKernelGGL((k_stage_lds<ORDER, KSH>), dim3(nwg), dim3(256), 0, st,
-                       P, G, stage, M);
+                       P, G, stage, M, kout);
     return hipGetLastError();
   }
   const int per_cu = ORDER == 4 ? 2 : 1;
@@ -1142,22 +1146,23 @@ hipError_t launch_stage_lds_k(const Patch& P, const Gauge& G, int stage,
   TileMap M32 = M;
   choose_blocks<ORDER>(M32, nwg32);
   hipLaunchKernelGGL((k_stage_lds_f32<ORDER, KSH>), dim3(nwg32), dim3(256), 0,
-                     st, P, G, stage, M32);
+                     st, P, G, stage, M32, kout);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_stage_lds_f64tiles<ORDER, KSH>), dim3(nwg), dim3(256),
-                     0, st, P, G, stage, M, int(tile_perm(M.ntiles)));
+                     0, st, P, G, stage, M, int(tile_perm(M.ntiles)), kout);
   return hipGetLastError();
 }
-// P.kout set: the kernels that also store the right-hand side at the
-// outermost interior layer.
+// kout set: the kernels that also store the right-hand side at the
+// outermost interior layer there.
 template <int ORDER>
 hipError_t launch_stage_lds(const Patch& P, const Gauge& G, int stage,
-                            int precision, int nwg_max, hipStream_t st) {
-  return P.kout ? launch_stage_lds_k<ORDER, true>(P, G, stage, precision,
-                                                  nwg_max, st)
-                : launch_stage_lds_k<ORDER, false>(P, G, stage, precision,
-                                                   nwg_max, st);
+                            int precision, int nwg_max, hipStream_t st,
+                            double* kout = nullptr) {
+  return kout ? launch_stage_lds_k<ORDER, true>(P, G, stage, precision,
+                                                nwg_max, st, kout)
+              : launch_stage_lds_k<ORDER, false>(P, G, stage, precision,
+                                                 nwg_max, st, nullptr);
 }
 
 // Explicit-variant launch of one static patch, and batched launches.

@@ -7,14 +7,14 @@ namespace bssn {
 
 hipError_t launch_stage_o8(const Patch& P, const Gauge& G, int periodic,
                            int stage, int precision, int path, int nwg,
-                           hipStream_t st) {
+                           hipStream_t st, double* kout) {
   const bool lds = !periodic && path != PATH_DIRECT && lds_path_ok<8>(P);
-  if (lds) return launch_stage_lds<8>(P, G, stage, precision, nwg, st);
-  if (P.kout) {
+  if (lds) return launch_stage_lds<8>(P, G, stage, precision, nwg, st, kout);
+  if (kout) {
     // the direct kernels do not store the shell's right-hand side: the
     // shell kernel does, before the stage
     Patch S = P;
-    S.out = P.kout;
+    S.out = kout;
     const hipError_t e = launch_shell_rhs_t<8>(S, G, st);
     if (e != hipSuccess) return e;
   }
