@@ -34,7 +34,8 @@
 // wave w = plane w of the tile); tiles are numbered x fastest and dealt to
 // the XCDs in contiguous eighths, so neighbouring tiles share an L2.  The
 // box (tile + M = order/2 on every side) holds e^{4 phi} and K/3 for the
-// whole pass (each thread re-reads only its own entries) and, per symmetric
+// whole pass (each thread re-reads only its own entries; at order 8 they
+// are kept in registers instead) and, per symmetric
 // component, g_ij and K_ij, converted on the way from memory into LDS.
 // Algorithmic bytes: 14 slots in (phi, gt_ij, K, At_ij), 2 out (re, im):
 // 128 B per interior point.  Roofline: HBM.
@@ -117,6 +118,34 @@ __device__ __forceinline__ double gdot(const double (&g)[6],
          g[4] * (a[1] * b[2] + a[2] * b[1]);
 }
 
+// e^{4 phi} and K/3 at this thread's box points (each thread reads only the
+// entries it wrote, so no barrier guards them): in registers (REG, order 8,
+// which frees LDS for a second workgroup per CU) or in LDS (order 4, whose
+// registers are needed for two waves per SIMD).
+template <bool REG, int NP>
+struct BoxScalars;
+template <int NP>
+struct BoxScalars<true, NP> {
+  double e[NP], k[NP];
+  __device__ __forceinline__ void set(int q, int, double ev, double kv) {
+    e[q] = ev;
+    k[q] = kv;
+  }
+  __device__ __forceinline__ double e4(int q, int) const { return e[q]; }
+  __device__ __forceinline__ double k3(int q, int) const { return k[q]; }
+};
+template <int NP>
+struct BoxScalars<false, NP> {
+  double* e;
+  double* k;
+  __device__ __forceinline__ void set(int, int p, double ev, double kv) {
+    e[p] = ev;
+    k[p] = kv;
+  }
+  __device__ __forceinline__ double e4(int, int p) const { return e[p]; }
+  __device__ __forceinline__ double k3(int, int p) const { return k[p]; }
+};
+
 // Everything a point keeps from the six component passes.
 struct Acc {
   double gm[6], K[6], dg[3][6], dK[3][6];
@@ -128,12 +157,12 @@ constexpr int PI[3] = {0, 0, 1}, PJ[3] = {1, 2, 2};  // pair P = (PI, PJ)
 // One symmetric component C of g_ij and K_ij: convert the box from memory
 // into LDS, then form this point's value, first derivatives and (into the
 // Riemann pair components) second derivatives.
-template <int ORDER, int C, int NP>
+template <int ORDER, int C, int NP, class BS>
 __device__ __forceinline__ void component(Acc& a, const double* u, int64_t sf,
                                           const int32_t (&sidx)[NP], int t,
                                           int c0, const double (&ih)[3],
-                                          const double* e4s, const double* tks,
-                                          double* gs, double* ks) {
+                                          const BS& bs, double* gs,
+                                          double* ks) {
   using B = Box<ORDER>;
   constexpr int M = B::M;
   constexpr int st[3] = {1, B::X, B::X * B::Y};
@@ -146,8 +175,8 @@ __device__ __forceinline__ void component(Acc& a, const double* u, int64_t sf,
       if (sidx[q] >= 0) {
         const double gt = u[(GXX + C) * sf + sidx[q]];
         const double at = u[(AXX + C) * sf + sidx[q]];
-        gv = e4s[p] * gt;
-        kv = e4s[p] * (at + gt * tks[p]);
+        gv = bs.e4(q, p) * gt;
+        kv = bs.e4(q, p) * (at + gt * bs.k3(q, p));
       }
       gs[p] = gv;
       ks[p] = kv;
@@ -213,7 +242,9 @@ template <int ORDER>
 __global__ void __launch_bounds__(256) k_psi4(const Psi4Args A) {
   using B = Box<ORDER>;
   constexpr int M = B::M;
-  __shared__ double e4s[B::N], tks[B::N], gs[B::N], ks[B::N];
+  constexpr bool kReg = ORDER == 8;
+  __shared__ double gs[B::N], ks[B::N];
+  __shared__ double lds_scalars[kReg ? 2 : 2 * B::N];
 
   // tile of this workgroup: the XCD (block id mod 8) takes a contiguous
   // eighth of the x-fastest tile numbering
@@ -250,6 +281,11 @@ __global__ void __launch_bounds__(256) k_psi4(const Psi4Args A) {
   }
   const double* u = A.u;
   const int64_t sf = A.sf;
+  BoxScalars<kReg, NP> bs;
+  if constexpr (!kReg) {
+    bs.e = lds_scalars;
+    bs.k = lds_scalars + B::N;
+  }
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
     const int p = t + 256 * q;
@@ -259,8 +295,7 @@ __global__ void __launch_bounds__(256) k_psi4(const Psi4Args A) {
         e = exp(4.0 * u[PHI * sf + sidx[q]]);
         k3 = u[TRK * sf + sidx[q]] / 3.0;
       }
-      e4s[p] = e;
-      tks[p] = k3;
+      bs.set(q, p, e, k3);
     }
   }
 
@@ -277,12 +312,12 @@ __global__ void __launch_bounds__(256) k_psi4(const Psi4Args A) {
   for (int P = 0; P < 3; ++P)
 #pragma unroll
     for (int Q = 0; Q < 3; ++Q) a.R[P][Q] = 0.0;
-  component<ORDER, 0>(a, u, sf, sidx, t, c0, ih, e4s, tks, gs, ks);
-  component<ORDER, 1>(a, u, sf, sidx, t, c0, ih, e4s, tks, gs, ks);
-  component<ORDER, 2>(a, u, sf, sidx, t, c0, ih, e4s, tks, gs, ks);
-  component<ORDER, 3>(a, u, sf, sidx, t, c0, ih, e4s, tks, gs, ks);
-  component<ORDER, 4>(a, u, sf, sidx, t, c0, ih, e4s, tks, gs, ks);
-  component<ORDER, 5>(a, u, sf, sidx, t, c0, ih, e4s, tks, gs, ks);
+  component<ORDER, 0>(a, u, sf, sidx, t, c0, ih, bs, gs, ks);
+  component<ORDER, 1>(a, u, sf, sidx, t, c0, ih, bs, gs, ks);
+  component<ORDER, 2>(a, u, sf, sidx, t, c0, ih, bs, gs, ks);
+  component<ORDER, 3>(a, u, sf, sidx, t, c0, ih, bs, gs, ks);
+  component<ORDER, 4>(a, u, sf, sidx, t, c0, ih, bs, gs, ks);
+  component<ORDER, 5>(a, u, sf, sidx, t, c0, ih, bs, gs, ks);
   const double(&gm)[6] = a.gm;
   const double(&K)[6] = a.K;
   const double(&dg)[3][6] = a.dg;
