@@ -8,8 +8,8 @@ vacuum) projected onto the fiducial null tetrad
 u the unit normal of the slice; the spatial triad starts from
     phi~ = (-y, x, 0),  r~ = (x, y, z),
     theta~^i = sqrt(det gamma) gamma^ik eps_klm phi~^l r~^m
-and is made orthonormal (with the 3-metric) starting with phi~, Gram-Schmidt
-at each step (r against phi, then theta against phi and r).  Psi_4 is
+and is made orthonormal with the 3-metric by Gram-Schmidt, phi~ normalised
+first (then r against phi, then theta against phi and r).  Psi_4 is
 evaluated in the printed 3+1 form
     Psi_4 = R_ijkl n^i mb^j n^k mb^l
           + 2 R_0jkl (n^0 mb^j n^k mb^l - mb^0 n^j n^k mb^l)
@@ -23,8 +23,8 @@ the sign of d_t gamma_ij = -2 alpha K_ij + ...):
     R_0jkl = D_k K_jl - D_l K_jk,
     R_0j0l = 3R_jl + K K_jl - K_jm K^m_l.
 
-Discretisation (reading, the paper names "the metric components and its
-derivatives"): the ADM variables are formed from the BSSN state pointwise
+Discretisation (a reading: the paper evaluates Psi_4 from the metric and
+its derivatives without fixing a scheme): the ADM variables are formed from the BSSN state pointwise
 by inverting the paper's definitions, gamma_ij = e^{4 phi} gt_ij and
 K_ij = e^{4 phi} (At_ij + gt_ij K / 3), at every storage point; at interior
 points gamma_ij is differenced with the evolution's centred stencils (first,
@@ -134,7 +134,7 @@ def tetrad(gam, x):
     eps[0, 1, 2] = eps[1, 2, 0] = eps[2, 0, 1] = 1.0
     eps[0, 2, 1] = eps[2, 1, 0] = eps[1, 0, 2] = -1.0
     th = sdet * np.einsum("ik...,klm,l...,m...->i...", ginv, eps, phi, r)
-    # Gram-Schmidt, starting with phi
+    # Gram-Schmidt: phi first, then r, then theta
     phi = phi / np.sqrt(dot(phi, phi))
     r = r - dot(r, phi) * phi
     r = r / np.sqrt(dot(r, r))
