@@ -207,11 +207,13 @@ __device__ __forceinline__ uint32_t lds_addr(const void* p) {
   return uint32_t(reinterpret_cast<uintptr_t>(
       (const __attribute__((address_space(3))) char*)(p)));
 }
+// (opaque base and stride, as for slot_rsrc)
 __device__ __forceinline__ v4i slot_dma_rsrc(const double* u, int64_t sf,
                                              int s, int32_t nbytes) {
   const double* b = u;
-  asm volatile("" : "+s"(b));
-  return dma_rsrc(b + s * sf, nbytes);
+  int64_t o = sf;
+  asm volatile("" : "+s"(b), "+s"(o));
+  return dma_rsrc(b + s * o, nbytes);
 }
 
 // Slots whose stencils include mixed second derivatives (gt_ij, phi,
@@ -332,35 +334,46 @@ __device__ __forceinline__ void vm_wait_extra(int extra) {
 // short stretch of algebra remain.
 constexpr int kEpiSlot = BETX;
 
-// Per-lane entry positions of the shared mixed-derivative scratch: for each
-// chunk this lane's wave fills (chunk 4r + wave), the box element of the
-// entry's lowest tap (y - M for y sums, z - M for z sums).
+// Box element of the lowest tap (y - M for y sums, z - M for z sums) of
+// entry `lane` of chunk c of the shared mixed-derivative scratch (MixGeo
+// layout).  c is uniform over the wave; the three kinds of chunk (PX, QX,
+// PZ) take separate code, so that where c is known at compile time only
+// one remains.
 template <class Geo>
-__device__ __forceinline__ void mix_entries(int wave, int lane,
-                                            int (&o)[MixGeo<Geo>::NR]) {
+__device__ __forceinline__ int mix_entry(int c, int lane) {
   using MG = MixGeo<Geo>;
   constexpr int M = MG::M, XW = MG::XW, R = Geo::R, W = Geo::W, H = Geo::H;
-#pragma unroll
-  for (int r = 0; r < MG::NR; ++r) {
-    const int e = (4 * r + wave) * 64 + lane;
-    int x, y, z;  // box coordinates of the lowest tap
-    if (e < 2 * MG::NX) {  // PX (y sums) or QX (z sums), x-extended
-      const int i = e < MG::NX ? e : e - MG::NX;
-      const int ix = i % XW, ty = (i / XW) % Geo::TY, tz = i / (XW * Geo::TY);
-      x = ix - M + R + 1;
-      y = ty + R - (e < MG::NX ? M : 0);
-      z = tz + R - (e < MG::NX ? 0 : M);
-    } else {  // PZ: y sums on the planes beyond the tile
-      const int i = e - 2 * MG::NX;
-      const int tx = i % Geo::TX, ty = (i / Geo::TX) % Geo::TY;
-      const int pz = i / (Geo::TX * Geo::TY);
-      const int zr = pz < M ? pz - M : Geo::TZ + pz - M;
-      x = tx + R + 1;
-      y = ty + R - M;
-      z = zr + R;
-    }
-    o[r] = e < MG::NE ? (z * H + y) * W + x : 0;
+  if (c < 2 * MG::NX / 64) {  // PX (y sums) or QX (z sums), x-extended
+    // entry i = q XW + ix with q = tz TY + ty: its box element is
+    // tz (H W) + ty W + ix + const = tz (H - TY) W + q (W - XW) + i + const
+    const bool qx = c >= MG::NX / 64;
+    const unsigned i =
+        unsigned((qx ? c - MG::NX / 64 : c) * 64) + unsigned(lane);
+    const unsigned q = i / unsigned(XW), tz = q / unsigned(Geo::TY);
+    constexpr int C0 = (R * H + R - M) * W + R + 1 - M;  // PX: (R, R - M)
+    constexpr int C1 = ((R - M) * H + R) * W + R + 1 - M;  // QX: (R - M, R)
+    return int(tz * unsigned((H - Geo::TY) * W) + q * unsigned(W - XW) + i) +
+           (qx ? C1 : C0);
   }
+  // PZ: y sums on the planes beyond the tile; a chunk is one plane
+  static_assert(Geo::TX * Geo::TY == 64, "one PZ plane per chunk");
+  const int pz = c - 2 * MG::NX / 64;
+  const int zr = pz < M ? pz - M : Geo::TZ + pz - M;
+  return ((zr + R) * H + (lane >> 4) + R - M) * W + (lane & 15) + R + 1;
+}
+
+// Distinct empty asm at both ends of each code path of a uniform branch,
+// so that the compiler keeps the paths apart (each with its own immediate
+// LDS offsets) instead of merging them into one with selected addresses.
+template <int K>
+__device__ __forceinline__ void path_mark();
+template <>
+__device__ __forceinline__ void path_mark<0>() {
+  asm volatile("; path 0");
+}
+template <>
+__device__ __forceinline__ void path_mark<1>() {
+  asm volatile("; path 1");
 }
 
 // Loader used by point_rhs inside the pipelined kernel.  Phase p of the
@@ -490,6 +503,26 @@ struct LdLds {
   // written to LDS, and read back after a barrier by the lanes that need
   // it, instead of each lane forming the 2M inner sums of each pair itself.
   // Every wave calls it at the same phases (it holds a barrier).
+  //
+  // Addressing: the taps of an inner sum are read from one opaque VGPR base
+  // with immediate offsets.
+  template <int ORDER, typename T, int S>
+  __device__ __forceinline__ T inner_sum(const lds_double* b) const {
+    using F = FD<ORDER>;
+    constexpr int M = F::M;
+    asm volatile("" : "+v"(b));
+    double t[2 * M];
+#pragma unroll
+    for (int j = 1; j <= M; ++j) {
+      t[2 * j - 2] = b[(M + j) * S];
+      t[2 * j - 1] = b[(M - j) * S];
+    }
+    T v = T(0);
+#pragma unroll
+    for (int j = 1; j <= M; ++j)
+      v += T(F::a(j)) * T(t[2 * j - 2] - t[2 * j - 1]);
+    return v;
+  }
   template <int ORDER, typename T>
   __device__ __forceinline__ void mixed3(T ihxy, T ihxz, T ihyz, T& dxy,
                                          T& dxz, T& dyz) const {
@@ -499,27 +532,26 @@ struct LdLds {
     constexpr int SY = Geo::W, SZ = Geo::W * Geo::H;
     typedef __attribute__((address_space(3))) T lds_t;
     lds_t* mx = (lds_t*)mix;
-    // positions derived from an opaque copy of the lane number, so that
-    // they are formed here rather than hoisted out of the tile loop (where
-    // they would hold registers through every phase)
+    // the lane number through an opaque copy, so that the entry positions
+    // are formed here rather than hoisted out of the tile loop (where they
+    // would hold registers through every phase); the wave index masked to
+    // its range, so that a round's chunk kind folds where it can
     int ln = lane;
     asm volatile("" : "+v"(ln));
-    int eo[MG::NR];
-    mix_entries<Geo>(wave, ln, eo);
+    const int w = wave & 3;
 #pragma unroll
     for (int r = 0; r < MG::NR; ++r) {
-      const int c = 4 * r + wave;  // chunk: uniform over the wave
+      const int c = 4 * r + w;  // chunk: uniform over the wave
       if (4 * r + 3 >= MG::NC && c >= MG::NC) continue;
-      const lds_double* b = box + eo[r];
-      T v = T(0);
+      T v;
       if (c >= NX / 64 && c < 2 * NX / 64) {  // QX: sums along z
-#pragma unroll
-        for (int j = 1; j <= M; ++j)
-          v += T(F::a(j)) * T(b[(M + j) * SZ] - b[(M - j) * SZ]);
+        path_mark<0>();
+        v = inner_sum<ORDER, T, SZ>(box + mix_entry<Geo>(c, ln));
+        path_mark<0>();
       } else {  // PX, PZ: sums along y
-#pragma unroll
-        for (int j = 1; j <= M; ++j)
-          v += T(F::a(j)) * T(b[(M + j) * SY] - b[(M - j) * SY]);
+        path_mark<1>();
+        v = inner_sum<ORDER, T, SY>(box + mix_entry<Geo>(c, ln));
+        path_mark<1>();
       }
       mx[c * 64 + lane] = v;
     }

@@ -162,12 +162,24 @@ __device__ __forceinline__ T star(const L& ld, int s,
   constexpr int R = F::R, M = F::M;
   const double c0 = ld.c(s);
   T adv = T(0);
+  // raw taps of two axes (index WI<R>(k)): the taps of axis a + 1 are read
+  // before the arithmetic of axis a, so that their LDS latency hides behind
+  // it
+  double u[2][2 * R];
+#pragma unroll
+  for (int k = -R; k <= R; ++k)
+    if (k != 0) u[0][WI<R>(k)] = ld.ax(s, 0, k);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
+    if (a < 2) {
+#pragma unroll
+      for (int k = -R; k <= R; ++k)
+        if (k != 0) u[(a + 1) & 1][WI<R>(k)] = ld.ax(s, a + 1, k);
+    }
     double d[2 * R + 1];
 #pragma unroll
     for (int k = -R; k <= R; ++k)
-      if (k != 0) d[R + k] = ld.ax(s, a, k) - c0;
+      if (k != 0) d[R + k] = u[a & 1][WI<R>(k)] - c0;
     if constexpr (D1) {
       T s1 = T(0);
 #pragma unroll
@@ -184,9 +196,15 @@ __device__ __forceinline__ T star(const L& ld, int s,
       d2[a] = s2 * ih2[a];
       keep(d2[a]);
     }
+    // two independent chains (taps below and above the point), so that
+    // the FMA latency of one hides behind the other
+    T lo = T(0), hi = T(0);
 #pragma unroll
-    for (int k = -R; k <= R; ++k)
-      if (k != 0) adv += cw[a][WI<R>(k)] * T(d[R + k]);
+    for (int k = 1; k <= R; ++k) {
+      lo += cw[a][WI<R>(-k)] * T(d[R - k]);
+      hi += cw[a][WI<R>(k)] * T(d[R + k]);
+    }
+    adv += lo + hi;
     keep(adv);
   }
   return adv;

@@ -27,16 +27,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const double* base,
                                            kRsrcWord3);
 }
 
-// Buffer resource of slot s built where it is used: the base goes through an
-// opaque scalar move, so the per-slot descriptors of a loop body are not
-// hoisted out of the loop (25 slots x 3 buffers x 4 SGPRs would be spilled
-// to VGPR lanes and moved back on every use).
+// Buffer resource of slot s built where it is used: the base and the slot
+// stride go through an opaque scalar move, so neither the per-slot
+// descriptors nor the per-slot offsets s*sf of a loop body are hoisted out
+// of the loop (25 slots x 3 buffers x 4 SGPRs, or 25 x 2 SGPRs, would be
+// spilled to VGPR lanes and moved back on every use).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t slot_rsrc(const double* u,
                                                             int64_t sf, int s,
                                                             int32_t nbytes) {
   const double* b = u;
-  asm volatile("" : "+s"(b));  // opaque here, so b + s*sf stays here too
-  return rsrc(b + s * sf, nbytes);
+  int64_t o = sf;
+  asm volatile("" : "+s"(b), "+s"(o));
+  return rsrc(b + s * o, nbytes);
 }
 
 __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r,
