@@ -505,23 +505,71 @@ struct LdLds {
   // Every wave calls it at the same phases (it holds a barrier).
   //
   // Addressing: the taps of an inner sum are read from one opaque VGPR base
-  // with immediate offsets.
-  template <int ORDER, typename T, int S>
-  __device__ __forceinline__ T inner_sum(const lds_double* b) const {
-    using F = FD<ORDER>;
-    constexpr int M = F::M;
-    asm volatile("" : "+v"(b));
-    double t[2 * M];
+  // with immediate offsets (a plain asm, so that it orders nothing else).
+  // Latency: the taps of round r + 1 are read before the arithmetic of
+  // round r, and the read-back taps of all three pairs before their sums.
+  template <int ORDER, int S>
+  __device__ __forceinline__ void entry_taps(const lds_double* b,
+                                             double (&t)[8]) const {
+    constexpr int M = FD<ORDER>::M;
+    static_assert(2 * M == 8, "eight taps per inner sum");
+    asm("" : "+v"(b));
 #pragma unroll
     for (int j = 1; j <= M; ++j) {
       t[2 * j - 2] = b[(M + j) * S];
       t[2 * j - 1] = b[(M - j) * S];
     }
+  }
+  // Kind of the chunks of round RR (chunks 4 RR .. 4 RR + 3, one per wave):
+  // 0 all z sums (QX), 1 all y sums (PX, PZ), 2 both (chosen per wave).
+  template <int RR>
+  static constexpr int round_kind() {
+    using MG = MixGeo<Geo>;
+    int nz = 0, ny = 0;
+    for (int w = 0; w < 4; ++w) {
+      const int c = 4 * RR + w;
+      if (c >= MG::NX / 64 && c < 2 * MG::NX / 64)
+        ++nz;
+      else
+        ++ny;
+    }
+    return ny == 0 ? 0 : (nz == 0 ? 1 : 2);
+  }
+  template <int ORDER, int RR>
+  __device__ __forceinline__ void round_taps(int w, int ln,
+                                             double (&t)[8]) const {
+    using MG = MixGeo<Geo>;
+    constexpr int SY = Geo::W, SZ = Geo::W * Geo::H, K = round_kind<RR>();
+    const int c = 4 * RR + w;
+    if constexpr (K == 0) {
+      entry_taps<ORDER, SZ>(box + mix_entry<Geo>(c, ln), t);
+    } else if constexpr (K == 1) {
+      entry_taps<ORDER, SY>(box + mix_entry<Geo>(c, ln), t);
+    } else if (c >= MG::NX / 64 && c < 2 * MG::NX / 64) {
+      path_mark<0>();
+      entry_taps<ORDER, SZ>(box + mix_entry<Geo>(c, ln), t);
+      path_mark<0>();
+    } else {
+      path_mark<1>();
+      entry_taps<ORDER, SY>(box + mix_entry<Geo>(c, ln), t);
+      path_mark<1>();
+    }
+  }
+  // Rounds RR .. NR - 1 of the inner sums; cur holds the taps of round RR.
+  template <int ORDER, typename T, int RR>
+  __device__ __forceinline__ void rounds(int w, int ln, double (&cur)[8],
+                                         double (&nxt)[8]) const {
+    using F = FD<ORDER>;
+    using MG = MixGeo<Geo>;
+    constexpr int M = F::M;
+    typedef __attribute__((address_space(3))) T lds_t;
+    if constexpr (RR + 1 < MG::NR) round_taps<ORDER, RR + 1>(w, ln, nxt);
     T v = T(0);
 #pragma unroll
     for (int j = 1; j <= M; ++j)
-      v += T(F::a(j)) * T(t[2 * j - 2] - t[2 * j - 1]);
-    return v;
+      v += T(F::a(j)) * T(cur[2 * j - 2] - cur[2 * j - 1]);
+    ((lds_t*)mix)[(4 * RR + w) * 64 + lane] = v;
+    if constexpr (RR + 1 < MG::NR) rounds<ORDER, T, RR + 1>(w, ln, nxt, cur);
   }
   template <int ORDER, typename T>
   __device__ __forceinline__ void mixed3(T ihxy, T ihxz, T ihyz, T& dxy,
@@ -529,7 +577,7 @@ struct LdLds {
     using F = FD<ORDER>;
     using MG = MixGeo<Geo>;
     constexpr int M = MG::M, XW = MG::XW, NX = MG::NX;
-    constexpr int SY = Geo::W, SZ = Geo::W * Geo::H;
+    static_assert(MG::NC == 4 * MG::NR, "whole rounds of chunks");
     typedef __attribute__((address_space(3))) T lds_t;
     lds_t* mx = (lds_t*)mix;
     // the lane number through an opaque copy, so that the entry positions
@@ -539,47 +587,41 @@ struct LdLds {
     int ln = lane;
     asm volatile("" : "+v"(ln));
     const int w = wave & 3;
-#pragma unroll
-    for (int r = 0; r < MG::NR; ++r) {
-      const int c = 4 * r + w;  // chunk: uniform over the wave
-      if (4 * r + 3 >= MG::NC && c >= MG::NC) continue;
-      T v;
-      if (c >= NX / 64 && c < 2 * NX / 64) {  // QX: sums along z
-        path_mark<0>();
-        v = inner_sum<ORDER, T, SZ>(box + mix_entry<Geo>(c, ln));
-        path_mark<0>();
-      } else {  // PX, PZ: sums along y
-        path_mark<1>();
-        v = inner_sum<ORDER, T, SY>(box + mix_entry<Geo>(c, ln));
-        path_mark<1>();
-      }
-      mx[c * 64 + lane] = v;
+    {
+      double ta[8], tb[8];
+      round_taps<ORDER, 0>(w, ln, ta);
+      rounds<ORDER, T, 0>(w, ln, ta, tb);
     }
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
     const int tx = ln & 15, ty = ln >> 4;
     // lowest x tap (x - M) of this point in PX and QX
-    const lds_t* px = mx + (wave * Geo::TY + ty) * XW + tx;
-    T a = T(0), q = T(0);
-#pragma unroll
-    for (int i = 1; i <= M; ++i) {
-      a += T(F::a(i)) * (px[M + i] - px[M - i]);
-      q += T(F::a(i)) * (px[NX + M + i] - px[NX + M - i]);
-    }
-    dxy = a * ihxy;
-    dxz = q * ihxz;
+    const lds_t* px = mx + (w * Geo::TY + ty) * XW + tx;
+    asm("" : "+v"(px));
     // y sums at (x, y, z + k): PX inside the tile, PZ on the planes beyond
     const lds_t* pxc = mx + ty * XW + tx + M;
     const lds_t* pzc = mx + 2 * NX + ty * Geo::TX + tx;
-    T d = T(0);
+    T ta[2 * M], tq[2 * M], td[2 * M];
 #pragma unroll
     for (int i = 1; i <= M; ++i) {
-      const int zp = wave + i, zm = wave - i;  // uniform
-      const T vp = zp < Geo::TZ ? pxc[zp * Geo::TY * XW]
-                                : pzc[(zp - Geo::TZ + M) * Geo::TY * Geo::TX];
-      const T vm = zm >= 0 ? pxc[zm * Geo::TY * XW]
-                           : pzc[(zm + M) * Geo::TY * Geo::TX];
-      d += T(F::a(i)) * (vp - vm);
+      ta[2 * i - 2] = px[M + i];
+      ta[2 * i - 1] = px[M - i];
+      tq[2 * i - 2] = px[NX + M + i];
+      tq[2 * i - 1] = px[NX + M - i];
+      const int zp = w + i, zm = w - i;  // uniform
+      td[2 * i - 2] = zp < Geo::TZ ? pxc[zp * Geo::TY * XW]
+                                   : pzc[(zp - Geo::TZ + M) * Geo::TY * Geo::TX];
+      td[2 * i - 1] = zm >= 0 ? pxc[zm * Geo::TY * XW]
+                              : pzc[(zm + M) * Geo::TY * Geo::TX];
     }
+    T a = T(0), q = T(0), d = T(0);
+#pragma unroll
+    for (int i = 1; i <= M; ++i) {
+      a += T(F::a(i)) * (ta[2 * i - 2] - ta[2 * i - 1]);
+      q += T(F::a(i)) * (tq[2 * i - 2] - tq[2 * i - 1]);
+      d += T(F::a(i)) * (td[2 * i - 2] - td[2 * i - 1]);
+    }
+    dxy = a * ihxy;
+    dxz = q * ihxz;
     dyz = d * ihyz;
     keep(dxy);
     keep(dxz);
@@ -706,7 +748,7 @@ __device__ __forceinline__ void tile_point(const LD& ld, const Patch& P,
   if (EARLY) {
     if (active) epilogue_store<T>(P, stage, r, vc, nbytes, ld.un, ld.ac);
   } else {
-    epilogue_all<T>(P, stage, r, ld.vc_epi, nbytes, active);
+    epilogue_all<T>(P, stage, r, ld.vc_epi, nbytes);
   }
   if constexpr (KSH) {
     if (active && shell) {
@@ -815,9 +857,13 @@ __device__ __forceinline__ void lds_tiles(const Patch& P, const Gauge& G,
     }
     prev_loads =
         !computed ? 0 : (early ? ld.epi_loads : epilogue_loads(stage));
-    prev_stores = computed && __builtin_amdgcn_ballot_w64(active) != 0
-                      ? epilogue_stores(stage)
-                      : 0;
+    // (without early loads every lane stores, inactive ones beyond the
+    // buffer; with them only active lanes do, and a wave without any
+    // issues none)
+    prev_stores =
+        computed && (!early || __builtin_amdgcn_ballot_w64(active) != 0)
+            ? epilogue_stores(stage)
+            : 0;
     // the shell stores of this wave, if any lane made them (a wave whose
     // lanes all skip them may still issue them with no lane enabled, which
     // only makes the next waits longer than needed)

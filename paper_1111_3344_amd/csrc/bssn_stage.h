@@ -217,19 +217,37 @@ __device__ __forceinline__ void epilogue_store(const Patch& P, int stage,
   }
 }
 
-// The whole epilogue with the loads issued by every lane (vc_all: the
-// point's offset, or beyond the buffer for inactive lanes, which then read
-// 0 without traffic) and the stores by active lanes only; the number of
-// loads a wave issues is then exactly epilogue_loads(stage).
+// The whole epilogue with the loads and the stores issued by every lane
+// (vc_all: the point's offset, or beyond the buffer for inactive lanes,
+// which then read 0 and whose stores are dropped, without traffic); the
+// numbers of loads and stores a wave issues are then exactly
+// epilogue_loads(stage) and epilogue_stores(stage).  Each stage has its own
+// path, loads and stores together, so that no path leaves a load pending
+// that the compiler would wait for where its register is next written.
 template <typename T>
 __device__ __forceinline__ void epilogue_all(const Patch& P, int stage,
                                              const T (&r)[NSLOT],
-                                             uint32_t vc_all, int32_t nbytes,
-                                             bool active) {
+                                             uint32_t vc_all, int32_t nbytes) {
   double un[NSLOT], ac[NSLOT];
-  epilogue_load(P, stage, vc_all, nbytes, un, ac);
-  BSSN_PHASE();  // loads above, stores below
-  if (active) epilogue_store<T>(P, stage, r, vc_all, nbytes, un, ac);
+  if (stage == ST_RHS) {
+    epilogue_store<T>(P, ST_RHS, r, vc_all, nbytes, un, ac);
+  } else if (stage == ST_0) {
+    epilogue_load(P, ST_0, vc_all, nbytes, un, ac);
+    BSSN_PHASE();  // loads above, stores below
+    epilogue_store<T>(P, ST_0, r, vc_all, nbytes, un, ac);
+  } else if (stage == ST_3) {
+    epilogue_load(P, ST_3, vc_all, nbytes, un, ac);
+    BSSN_PHASE();
+    epilogue_store<T>(P, ST_3, r, vc_all, nbytes, un, ac);
+  } else if (stage == ST_1) {
+    epilogue_load(P, ST_1, vc_all, nbytes, un, ac);
+    BSSN_PHASE();
+    epilogue_store<T>(P, ST_1, r, vc_all, nbytes, un, ac);
+  } else {
+    epilogue_load(P, ST_2, vc_all, nbytes, un, ac);
+    BSSN_PHASE();
+    epilogue_store<T>(P, ST_2, r, vc_all, nbytes, un, ac);
+  }
 }
 
 template <typename T>
