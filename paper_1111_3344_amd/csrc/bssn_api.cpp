@@ -373,6 +373,7 @@ int radiative_args(const bssn_grid* grid, const double* x0, const double* v0,
     A.n[a] = grid->n[a];
     A.origin[a] = grid->origin[a];
     A.h[a] = grid->h[a];
+    A.i2h[a] = 1.0 / (2.0 * grid->h[a]);
   }
   A.ghost = grid->ghost;
   A.sy = grid->sy;

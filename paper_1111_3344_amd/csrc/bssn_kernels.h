@@ -115,6 +115,7 @@ struct RadiativeArgs {
   int64_t sy, sz, sf;
   double origin[3];
   double h[3];
+  double i2h[3];  // 1 / (2 h), per axis
   double x0[NSLOT];
   double v0[NSLOT];
   int32_t power;

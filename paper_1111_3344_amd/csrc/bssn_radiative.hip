@@ -23,14 +23,14 @@ namespace bssn {
 namespace {
 
 // Second-order first derivative of v at storage index j (of N) along the
-// axis with element stride st, spacing h.
+// axis with element stride st; i2h = 1 / (2 h).
 __device__ __forceinline__ double rad_deriv(const double* v, int64_t idx,
                                             int j, int N, int64_t st,
-                                            double h) {
-  if (j > 0 && j < N - 1) return (v[idx + st] - v[idx - st]) / (2.0 * h);
+                                            double i2h) {
+  if (j > 0 && j < N - 1) return (v[idx + st] - v[idx - st]) * i2h;
   if (j == 0)
-    return (-3.0 * v[idx] + 4.0 * v[idx + st] - v[idx + 2 * st]) / (2.0 * h);
-  return (3.0 * v[idx] - 4.0 * v[idx - st] + v[idx - 2 * st]) / (2.0 * h);
+    return (-3.0 * v[idx] + 4.0 * v[idx + st] - v[idx + 2 * st]) * i2h;
+  return (3.0 * v[idx] - 4.0 * v[idx - st] + v[idx - 2 * st]) * i2h;
 }
 
 struct RadPoint {
@@ -48,14 +48,47 @@ __device__ __forceinline__ RadPoint rad_wave(const RadiativeArgs& A, int s,
   const double y = A.origin[1] + (j - g) * A.h[1];
   const double z = A.origin[2] + (k - g) * A.h[2];
   const double r = sqrt(x * x + y * y + z * z);
-  const double xd = x * rad_deriv(v, idx, i, N0, 1, A.h[0]) +
-                    y * rad_deriv(v, idx, j, N1, A.sy, A.h[1]) +
-                    z * rad_deriv(v, idx, k, N2, A.sz, A.h[2]);
-  const double v0 = A.v0[s];
+  const double xd = x * rad_deriv(v, idx, i, N0, 1, A.i2h[0]) +
+                    y * rad_deriv(v, idx, j, N1, A.sy, A.i2h[1]) +
+                    z * rad_deriv(v, idx, k, N2, A.sz, A.i2h[2]);
   RadPoint p;
-  p.S = -v0 * xd / r - v0 * (v[idx] - A.x0[s]) / r;
+  p.S = -A.v0[s] * (xd + (v[idx] - A.x0[s])) / r;
   p.r = r;
   return p;
+}
+
+// Storage point (i, j, k) of boundary point t (32-bit counts, checked on the
+// host), numbered as described below; false past the last one.
+__device__ __forceinline__ bool boundary_point(const RadiativeArgs& A,
+                                               uint32_t t, uint32_t na,
+                                               uint32_t nb, uint32_t nc,
+                                               int& i, int& j, int& k) {
+  const int g = A.ghost;
+  const uint32_t N0 = A.n[0] + 2 * g, N1 = A.n[1] + 2 * g;
+  if (t < na) {
+    const uint32_t plane = t / (N0 * N1), m = t - plane * (N0 * N1);
+    k = int(plane) < g ? int(plane) : int(plane) - g + A.n[2] + g;
+    j = int(m / N0);
+    i = int(m - uint32_t(j) * N0);
+  } else if (t < na + nb) {
+    const uint32_t u = t - na, row = u / N0;
+    i = int(u - row * N0);
+    const uint32_t rk = row / uint32_t(2 * g);
+    const int jr = int(row - rk * uint32_t(2 * g));
+    k = g + int(rk);
+    j = jr < g ? jr : jr - g + A.n[1] + g;
+  } else if (t < na + nb + nc) {
+    const uint32_t u = t - na - nb;
+    const uint32_t row = u / uint32_t(2 * g);
+    const int e = int(u - row * uint32_t(2 * g));
+    const uint32_t kk = row / uint32_t(A.n[1]);
+    j = g + int(row - kk * uint32_t(A.n[1]));
+    k = g + int(kk);
+    i = e < g ? e : e - g + A.n[0] + g;
+  } else {
+    return false;
+  }
+  return true;
 }
 
 // One thread per (boundary point, slot).  The boundary points (all ghost
@@ -68,34 +101,13 @@ __device__ __forceinline__ RadPoint rad_wave(const RadiativeArgs& A, int s,
 // interior box per axis), and the factors multiply to (r_root / r_p)^power:
 //   rhs(p) = S(p) + (r_root / r_p)^power (rhs(root) - S(root)).
 __global__ void __launch_bounds__(256)
-    k_radiative(const RadiativeArgs A, const int64_t na, const int64_t nb,
-                const int64_t nc) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    k_radiative(const RadiativeArgs A, const uint32_t na, const uint32_t nb,
+                const uint32_t nc) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   const int g = A.ghost;
-  const int N0 = A.n[0] + 2 * g, N1 = A.n[1] + 2 * g;
   int i, j, k;
-  if (t < na) {
-    const int64_t plane = t / (int64_t(N0) * N1), m = t % (int64_t(N0) * N1);
-    k = plane < g ? int(plane) : int(plane) - g + A.n[2] + g;
-    j = int(m / N0);
-    i = int(m % N0);
-  } else if (t < na + nb) {
-    const int64_t u = t - na, row = u / N0;
-    i = int(u % N0);
-    const int jr = int(row % (2 * g));
-    k = g + int(row / (2 * g));
-    j = jr < g ? jr : jr - g + A.n[1] + g;
-  } else if (t < na + nb + nc) {
-    const int64_t u = t - na - nb;
-    const int e = int(u % (2 * g));
-    const int64_t row = u / (2 * g);
-    j = g + int(row % A.n[1]);
-    k = g + int(row / A.n[1]);
-    i = e < g ? e : e - g + A.n[0] + g;
-  } else {
-    return;
-  }
+  if (!boundary_point(A, t, na, nb, nc, i, j, k)) return;
   const int ri = i < g ? g : (i >= A.n[0] + g ? A.n[0] + g - 1 : i);
   const int rj = j < g ? g : (j >= A.n[1] + g ? A.n[1] + g - 1 : j);
   const int rk = k < g ? g : (k >= A.n[2] + g ? A.n[2] + g - 1 : k);
@@ -118,33 +130,13 @@ __global__ void __launch_bounds__(256)
 //   s = 3:                      out = acc + dt/6 k
 __global__ void __launch_bounds__(256)
     k_radiative_stage(const RadiativeArgs A, const RadStage S,
-                      const int64_t na, const int64_t nb, const int64_t nc) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+                      const uint32_t na, const uint32_t nb,
+                      const uint32_t nc) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   const int g = A.ghost;
-  const int N0 = A.n[0] + 2 * g, N1 = A.n[1] + 2 * g;
   int i, j, k;
-  if (t < na) {
-    const int64_t plane = t / (int64_t(N0) * N1), m = t % (int64_t(N0) * N1);
-    k = plane < g ? int(plane) : int(plane) - g + A.n[2] + g;
-    j = int(m / N0);
-    i = int(m % N0);
-  } else if (t < na + nb) {
-    const int64_t u = t - na, row = u / N0;
-    i = int(u % N0);
-    const int jr = int(row % (2 * g));
-    k = g + int(row / (2 * g));
-    j = jr < g ? jr : jr - g + A.n[1] + g;
-  } else if (t < na + nb + nc) {
-    const int64_t u = t - na - nb;
-    const int e = int(u % (2 * g));
-    const int64_t row = u / (2 * g);
-    j = g + int(row % A.n[1]);
-    k = g + int(row / A.n[1]);
-    i = e < g ? e : e - g + A.n[0] + g;
-  } else {
-    return;
-  }
+  if (!boundary_point(A, t, na, nb, nc, i, j, k)) return;
   const int ri = i < g ? g : (i >= A.n[0] + g ? A.n[0] + g - 1 : i);
   const int rj = j < g ? g : (j >= A.n[1] + g ? A.n[1] + g - 1 : j);
   const int rk = k < g ? g : (k >= A.n[2] + g ? A.n[2] + g - 1 : k);
@@ -181,10 +173,12 @@ hipError_t launch_radiative_stage(const RadiativeArgs& A, const RadStage& S,
   const int64_t na = 2 * g * N1 * N0;
   const int64_t nb = int64_t(A.n[2]) * 2 * g * N0;
   const int64_t nc = int64_t(A.n[2]) * A.n[1] * 2 * g;
+  // boundary points are counted in 32 bits
+  if (na + nb + nc + 255 > 0xffffffffll) return hipErrorInvalidValue;
   const int64_t blocks = (na + nb + nc + 255) / 256;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_radiative_stage, dim3(unsigned(blocks), NSLOT),
-                     dim3(256), 0, st, A, S, na, nb, nc);
+                     dim3(256), 0, st, A, S, uint32_t(na), uint32_t(nb),
+                     uint32_t(nc));
   return hipGetLastError();
 }
 
@@ -194,10 +188,11 @@ hipError_t launch_radiative(const RadiativeArgs& A, hipStream_t st) {
   const int64_t na = 2 * g * N1 * N0;
   const int64_t nb = int64_t(A.n[2]) * 2 * g * N0;
   const int64_t nc = int64_t(A.n[2]) * A.n[1] * 2 * g;
+  // boundary points are counted in 32 bits
+  if (na + nb + nc + 255 > 0xffffffffll) return hipErrorInvalidValue;
   const int64_t blocks = (na + nb + nc + 255) / 256;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_radiative, dim3(unsigned(blocks), NSLOT), dim3(256), 0,
-                     st, A, na, nb, nc);
+                     st, A, uint32_t(na), uint32_t(nb), uint32_t(nc));
   return hipGetLastError();
 }
 
