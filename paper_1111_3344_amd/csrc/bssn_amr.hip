@@ -96,16 +96,22 @@ __global__ void __launch_bounds__(256)
 
 // One workgroup per (tile, slot): stage the tile's coarse region in LDS
 // with the time levels combined (Lagrange weights in time, the same for
-// every point), then each masked fine point of the box interpolates from
-// LDS, the tensor-product weights applied one axis at a time (x, y, z).
+// every point), then apply the tensor-product weights one axis at a time
+// over the bounding box of the tile's filled points, each pass from LDS to
+// LDS: x (every region row, the box's x points), y, then z at the filled
+// points only.  Each point's sum is the same sequence of multiply-adds as
+// the point-wise form (x innermost, then y, then z), with 12 LDS reads per
+// point instead of 64.
 __global__ void __launch_bounds__(256)
     k_amr_prolong(const AmrTile* __restrict__ tiles, const int64_t ntiles,
                   const AmrGeo* __restrict__ geo,
                   double* const* __restrict__ u, const AmrTime T) {
-  // the region, the coarse time levels already combined (the time weights
-  // are the same for every point); pitches 9 and 81 spread a wave's reads
-  // over the LDS banks
+  // the region (pitches 9 and 81 spread a wave's reads over the LDS banks),
+  // then the x sums [region z][region y][box x] and the y sums
+  // [region z][box y][box x], both with pitches 9 and 72
   __shared__ double reg[8 * 81];
+  __shared__ double xs[8 * 72];
+  __shared__ double ys[8 * 72];
   const int64_t nwg = gridDim.x, b = blockIdx.x;
   const int64_t id = (b % 8) * (nwg / 8) + b / 8;
   if (id >= ntiles * NSLOT) return;  // uniform over the workgroup
@@ -143,41 +149,61 @@ __global__ void __launch_bounds__(256)
       if (T.ntl > 2) t += T.w[2] * v[2][it];
       reg[lds_at[it]] = t;
     }
-  __syncthreads();
-  double* dst = u[dpatch] + int64_t(s) * gd.sf + tp->dst0;
   const int code = tp->code;
   const int ex = code & 1, ey = (code >> 1) & 1, ez = (code >> 2) & 1;
   const int r0x = tp->r0[0], r0y = tp->r0[1], r0z = tp->r0[2];
-  for (int pt = threadIdx.x; pt < 512; pt += 256) {
-    if (!((tp->mask[pt >> 6] >> (pt & 63)) & 1)) continue;
-    const int i = pt & 7, j = (pt >> 3) & 7, k = pt >> 6;
-    const int bx = r0x + (ex + i) / 2, by = r0y + (ey + j) / 2,
-              bz = r0z + (ez + k) / 2;
-    const int px = (ex + i) & 1, py = (ey + j) & 1, pz = (ez + k) & 1;
-    const double* c = reg + bz * 81 + by * 9 + bx;
-    double wx[4], wy[4], wz[4];
+  const int lx = tp->lo[0], ly = tp->lo[1], lz = tp->lo[2];
+  const int mx = tp->m[0], my = tp->m[1], mz = tp->m[2];
+  __syncthreads();
+  // x pass: entry (i, y, z) of an 8 x 8 x 8 index space, box x = lx + i
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      wx[m] = w_quarter(px, m);
-      wy[m] = w_quarter(py, m);
-      wz[m] = w_quarter(pz, m);
+  for (int it = 0; it < 2; ++it) {
+    const int e = threadIdx.x + it * 256;
+    const int i = e & 7, y = (e >> 3) & 7, z = e >> 6;
+    if (i < mx && y < cy && z < cz) {
+      const int fx = lx + i;
+      const int bx = r0x + (ex + fx) / 2, px = (ex + fx) & 1;
+      const double* c = reg + z * 81 + y * 9 + bx;
+      double xsum = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) xsum += w_quarter(px, ii) * c[ii];
+      xs[z * 72 + y * 9 + i] = xsum;
     }
-    // separable: x, then y, then z
-    double zsum = 0.0;
+  }
+  __syncthreads();
+  // y pass: entry (i, j, z), box y = ly + j
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
+  for (int it = 0; it < 2; ++it) {
+    const int e = threadIdx.x + it * 256;
+    const int i = e & 7, j = (e >> 3) & 7, z = e >> 6;
+    if (i < mx && j < my && z < cz) {
+      const int fy = ly + j;
+      const int by = r0y + (ey + fy) / 2, py = (ey + fy) & 1;
+      const double* c = xs + z * 72 + by * 9 + i;
       double ysum = 0.0;
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        double xsum = 0.0;
-#pragma unroll
-        for (int ii = 0; ii < 4; ++ii)
-          xsum += wx[ii] * c[kk * 81 + jj * 9 + ii];
-        ysum += wy[jj] * xsum;
-      }
-      zsum += wz[kk] * ysum;
+      for (int jj = 0; jj < 4; ++jj) ysum += w_quarter(py, jj) * c[jj * 9];
+      ys[z * 72 + j * 9 + i] = ysum;
     }
-    dst[k * gd.sz + j * gd.sy + i] = zsum;
+  }
+  __syncthreads();
+  // z pass at the filled points: entry (i, j, k), box z = lz + k
+  double* dst = u[dpatch] + int64_t(s) * gd.sf + tp->dst0;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int e = threadIdx.x + it * 256;
+    const int i = e & 7, j = (e >> 3) & 7, k = e >> 6;
+    const int fx = lx + i, fy = ly + j, fz = lz + k;
+    const int pt = fx + 8 * fy + 64 * fz;
+    if (i < mx && j < my && k < mz &&
+        ((tp->mask[pt >> 6] >> (pt & 63)) & 1)) {
+      const int bz = r0z + (ez + fz) / 2, pz = (ez + fz) & 1;
+      const double* c = ys + bz * 72 + j * 9 + i;
+      double zsum = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) zsum += w_quarter(pz, kk) * c[kk * 72];
+      dst[fz * gd.sz + fy * gd.sy + fx] = zsum;
+    }
   }
 }
 

@@ -66,6 +66,7 @@ struct TileAcc {
   uint64_t mask[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t bmin[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
   int64_t bmax[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
+  int lo[3] = {8, 8, 8}, hi[3] = {-1, -1, -1};  // filled points in the box
 };
 
 }  // namespace
@@ -210,6 +211,9 @@ int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
               for (int a = 0; a < 3; ++a) {
                 T.bmin[a] = b[a] < T.bmin[a] ? b[a] : T.bmin[a];
                 T.bmax[a] = b[a] > T.bmax[a] ? b[a] : T.bmax[a];
+                const int e = int(idx[a] % 8);
+                T.lo[a] = e < T.lo[a] ? e : T.lo[a];
+                T.hi[a] = e > T.hi[a] ? e : T.hi[a];
               }
               ++plan.nprolong[L];
               found = true;
@@ -231,9 +235,9 @@ int bssn_amr_plan_create(const bssn_amr_patch* patches, int npatch,
         t.spatch = c;
         int64_t o[3] = {kv.first[2] * 8, kv.first[1] * 8, kv.first[0] * 8};
         for (int a = 0; a < 3; ++a) {
-          const int64_t N = P.n[a] + 2 * P.g;
-          t.n[a] = uint8_t(N - o[a] < 8 ? N - o[a] : 8);
           t.c[a] = uint8_t(A.bmax[a] - A.bmin[a] + 4);
+          t.lo[a] = uint8_t(A.lo[a]);
+          t.m[a] = uint8_t(A.hi[a] - A.lo[a] + 1);
           const int64_t q0 = 2 * D[3 * L + a] + P.off[a] + o[a] - P.g;
           const int64_t f0 = floordiv(q0 - 1, 2);
           const int64_t e0 = q0 - 1 - 2 * f0;

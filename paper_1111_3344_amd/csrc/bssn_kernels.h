@@ -221,8 +221,9 @@ struct AmrTile {
   int32_t dpatch, spatch;
   int32_t r0[3];       // block base of box point 0, relative to the region
   int32_t code;        // bit a: (q - 1) mod 2 of box point 0 along axis a
-  uint8_t n[3], c[3];  // box extents (1..8), region extents (4..8)
-  uint8_t pad[2];
+  uint8_t c[3];        // region extents (4..8)
+  uint8_t lo[3], m[3]; // bounding box of the filled points: first, extent
+  uint8_t pad[7];
   uint64_t mask[8];    // point i + 8 j + 64 k of the box is filled
 };
 hipError_t launch_amr_fill(const AmrOp* ops, int64_t nops, const AmrGeo* geo,
