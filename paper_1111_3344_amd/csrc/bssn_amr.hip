@@ -4,8 +4,8 @@
 // the fine solution put back into the coarse grid).
 //
 // Lists built on the host (bssn_amr_plan.cpp):
-//   k_amr_fill      one thread per (op, slot): a ghost point copied from a
-//                   sibling patch's interior;
+//   k_amr_fill      one thread per op, all slots: a ghost point copied
+//                   from a sibling patch's interior;
 //   k_amr_prolong   one workgroup per (tile, slot): the prolonged ghost
 //                   points of an 8 x 8 x 8 box of a refined patch, the
 //                   tricubic interpolation of the coarse patch (per-axis
@@ -14,8 +14,8 @@
 //                   combined over up to three coarse time levels with
 //                   Lagrange weights in time, from the coarse region staged
 //                   in LDS;
-//   k_amr_restrict  one thread per (op, slot): a coarse interior point
-//                   covered by a refined patch: the
+//   k_amr_restrict  one thread per (op, group of slots): a coarse
+//                   interior point covered by a refined patch: the
 //                   tricubic midpoint interpolation (-1, 9, 9, -1)/16 of
 //                   the fine storage around it.
 // Memory-bound: a copy moves 16 B per slot; a tile reads its coarse region
@@ -42,34 +42,49 @@ __device__ __forceinline__ double w_mid(int m) {
 }
 
 // Workgroups are dealt to the 8 XCDs in turn (linear id mod 8).  Give each
-// XCD a contiguous eighth of the (slot, chunk of 256 ops) space instead, so
-// that neighbouring ops -- which read overlapping coarse blocks -- share an
-// L2.  nwg is the launch's workgroup count, a multiple of 8.
+// XCD a contiguous eighth of the (slot group, chunk of 256 ops) space
+// instead, so that neighbouring ops -- which read overlapping fine blocks
+// -- share an L2.  nwg is the launch's workgroup count, a multiple of 8.
 struct Work {
   int64_t t;  // op index
-  int s;      // slot
+  int g;      // slot group
   bool live;
 };
-__device__ __forceinline__ Work xcd_work(int64_t nops, int64_t nchunks) {
+__device__ __forceinline__ Work xcd_work(int64_t nops, int64_t nchunks,
+                                         int ngroups) {
   const int64_t nwg = gridDim.x, b = blockIdx.x;
   const int64_t id = (b % 8) * (nwg / 8) + b / 8;
   Work w;
-  w.s = int(id / nchunks);
+  w.g = int(id / nchunks);
   w.t = (id % nchunks) * 256 + threadIdx.x;
-  w.live = id < nchunks * NSLOT && w.t < nops;
+  w.live = id < nchunks * ngroups && w.t < nops;
   return w;
 }
 
+// Slots per restriction thread: the op is read once per group (with one
+// slot per thread the op list, larger than an L2, was read from HBM for
+// every slot).
+constexpr int RESTRICT_SLOTS = 5;
+static_assert(NSLOT % RESTRICT_SLOTS == 0, "slots per thread");
+
+// One thread per copy op, all 25 slots: the op is read once (a thread per
+// (op, slot) read it 25 times, from HBM, as the list outgrows the L2), the
+// slots' loads are all in flight before the first store.  A copy's source
+// (a sibling's interior) and destination (a ghost point) never overlap.
 __global__ void __launch_bounds__(256)
     k_amr_fill(const AmrOp* __restrict__ ops, const int64_t nops,
-               const int64_t nchunks, const AmrGeo* __restrict__ geo,
-               double* const* __restrict__ u) {
-  const Work w = xcd_work(nops, nchunks);
-  if (!w.live) return;
-  const AmrOp op = ops[w.t];
-  const AmrGeo gd = geo[op.dpatch], gs = geo[op.spatch];
-  u[op.dpatch][int64_t(w.s) * gd.sf + op.dst] =
-      u[op.spatch][int64_t(w.s) * gs.sf + op.src];
+               const AmrGeo* __restrict__ geo, double* const* __restrict__ u) {
+  const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (t >= nops) return;
+  const AmrOp op = ops[t];
+  const int64_t sfd = geo[op.dpatch].sf, sfs = geo[op.spatch].sf;
+  const double* src = u[op.spatch] + op.src;
+  double* dst = u[op.dpatch] + op.dst;
+  double v[NSLOT];
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) v[s] = src[s * sfs];
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) dst[s * sfd] = v[s];
 }
 
 __global__ void __launch_bounds__(256)
@@ -77,21 +92,25 @@ __global__ void __launch_bounds__(256)
                    const int64_t nchunks, const AmrGeo* __restrict__ geo,
                    double* const* __restrict__ coarse,
                    const double* const* __restrict__ fine) {
-  const Work w = xcd_work(nops, nchunks);
+  const Work w = xcd_work(nops, nchunks, NSLOT / RESTRICT_SLOTS);
   if (!w.live) return;
-  const int64_t t = w.t;
-  const int s = w.s;
-  const AmrOp op = ops[t];
+  const AmrOp op = ops[w.t];
   const AmrGeo gd = geo[op.dpatch], gs = geo[op.spatch];
-  const double* c = fine[op.spatch] + int64_t(s) * gs.sf + op.src;
-  double acc = 0.0;
-  for (int k = 0; k < 4; ++k)
+  const int s0 = w.g * RESTRICT_SLOTS;
+  const double* c0 = fine[op.spatch] + int64_t(s0) * gs.sf + op.src;
+  double* d0 = coarse[op.dpatch] + int64_t(s0) * gd.sf + op.dst;
+#pragma unroll 1
+  for (int q = 0; q < RESTRICT_SLOTS; ++q) {
+    const double* c = c0 + int64_t(q) * gs.sf;
+    double acc = 0.0;
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        acc += w_mid(k) * w_mid(j) * w_mid(i) * c[k * gs.sz + j * gs.sy + i];
-  coarse[op.dpatch][int64_t(s) * gd.sf + op.dst] = acc;
+        for (int i = 0; i < 4; ++i)
+          acc += w_mid(k) * w_mid(j) * w_mid(i) * c[k * gs.sz + j * gs.sy + i];
+    d0[int64_t(q) * gd.sf] = acc;
+  }
 }
 
 // One workgroup per (tile, slot): stage the tile's coarse region in LDS
@@ -223,11 +242,10 @@ hipError_t launch_amr_prolong(const AmrTile* tiles, int64_t ntiles,
 hipError_t launch_amr_fill(const AmrOp* ops, int64_t nops, const AmrGeo* geo,
                            double* const* u, hipStream_t st) {
   if (nops <= 0) return hipSuccess;
-  const int64_t nchunks = (nops + 255) / 256;
-  const int64_t nwg = (nchunks * NSLOT + 7) / 8 * 8;
+  const int64_t nwg = (nops + 255) / 256;
   if (nwg > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_amr_fill, dim3(unsigned(nwg)), dim3(256), 0, st, ops,
-                     nops, nchunks, geo, u);
+                     nops, geo, u);
   return hipGetLastError();
 }
 
@@ -236,7 +254,7 @@ hipError_t launch_amr_restrict(const AmrOp* ops, int64_t nops,
                                const double* const* fine, hipStream_t st) {
   if (nops <= 0) return hipSuccess;
   const int64_t nchunks = (nops + 255) / 256;
-  const int64_t nwg = (nchunks * NSLOT + 7) / 8 * 8;
+  const int64_t nwg = (nchunks * (NSLOT / RESTRICT_SLOTS) + 7) / 8 * 8;
   if (nwg > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_amr_restrict, dim3(unsigned(nwg)), dim3(256), 0, st,
                      ops, nops, nchunks, geo, coarse, fine);
