@@ -313,7 +313,8 @@ def time_amr_step(B, torch, g, wl, order, steps=3, precision=None,
             "hierarchy": "3 nested levels of the workload grid, h, h/2, h/4"
                          + (f", each cut into {split ** 3} patches"
                             if split > 1 else ""),
-            "level_stages": "batched over the level's patches" if batched
+            "level_stages": ("batched over the level's patches (a level "
+                             "of one patch: its rk4_stage)") if batched
                             else "one launch per patch"}
 
 

@@ -11,8 +11,9 @@ Python keeps the times and rotates the time-level buffers.
 
 A level's stages run either as one batched launch over all of its patches
 (batch_patches_stage of a plan per level and time-level rotation, the
-default) or as one rk4_stage per patch (batched=False); both run the same
-kernel arithmetic, so the two steppers agree bitwise.
+default; a level of one patch calls its rk4_stage directly) or as one
+rk4_stage per patch (batched=False); both run the same kernel arithmetic,
+so the two steppers agree bitwise.
 
 Per level L (spacing h_0 / 2^L, step dt_0 / 2^L) the stepper keeps three
 time levels of every patch: the current state and the two before it.  The
@@ -87,7 +88,10 @@ class BergerOliger:
         idx = [p for p, (lv, _) in enumerate(self.hier) if lv == L]
         ins = (self.prev, self.a, self.b, self.a)
         outs = (self.a, self.b, self.a, self.u)
-        plan = self._plan(L, idx, dt) if self.batched else None
+        # a level of one patch: its rk4_stage directly (the same kernel
+        # arithmetic; a plan's graph launch costs more than it saves there)
+        plan = (self._plan(L, idx, dt) if self.batched and len(idx) > 1
+                else None)
         for s in range(4):
             self._fill(L, self._level(L, ins[s]), T + STAGE_C[s] * dt)
             if plan is not None:

@@ -122,9 +122,10 @@ def test_berger_oliger_two_steps_match_oracle():
                                              ("two_level", 1)])
 def test_batched_level_stages_bitwise(hname, precision):
     """The stepper with every level's stages batched over its patches
-    (batch_patches_stage of per-level plans) equals the one launching
-    rk4_stage per patch, bitwise, over three level-0 steps: the same kernel
-    arithmetic, the same fills and restrictions."""
+    (batch_patches_stage of per-level plans; a level of one patch calls its
+    rk4_stage) equals the one launching rk4_stage per patch, bitwise, over
+    three level-0 steps: the same kernel arithmetic, the same fills and
+    restrictions."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1111_3344_amd import amr
@@ -146,7 +147,11 @@ def test_batched_level_stages_bitwise(hname, precision):
         torch.cuda.synchronize()
         res.append([x.cpu().numpy() for x in drv.u])
         if batched:
-            assert len(drv._plans) > 0
+            # plans exactly for the levels of several patches (a level of
+            # one patch calls its rk4_stage)
+            multi = {lv for lv, _ in hr
+                     if sum(1 for l2, _ in hr if l2 == lv) > 1}
+            assert {L for L, _ in drv._plans} == multi
     for p in range(len(hr)):
         assert np.array_equal(res[0][p], res[1][p]), p
         assert not np.array_equal(res[0][p], u0[p])
